@@ -1,0 +1,150 @@
+"""Seeded synthetic inputs for two vertically stacked 2D domains.
+
+This module only builds input states: it holds none of the solver's
+arithmetic (no fluxes, no time stepping) and imports neither the HIP binding
+nor the CPU oracle, so both can consume the same arrays.
+
+Background (per domain d): pressure p0 = 1/gamma, temperature T_d, density
+rho_d = gamma p0 / T_d (equation of state p = rho T / gamma), at rest.
+Perturbation: p = p0 (1 + A exp(-r^2 / w^2)) with r the x-periodic distance
+to a seeded centre (x_c, z_c); density follows isentropically,
+rho = rho_d (p / p0)^(1/gamma).  Values are point values at cell centres.
+Arrays are float64 [4, nz, nx] = (rho, rho u, rho w, rho E).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    nx: int
+    nz_lower: int
+    nz_upper: int
+    lx: float = 10.0            # x in (-lx/2, lx/2), periodic
+    lz_lower: float = 5.0       # lower domain z in (-lz_lower, 0)
+    lz_upper: float = 5.0       # upper domain z in (0, lz_upper)
+    fast_is_lower: bool = True
+    n_buffer: int = 4
+    base: int = 2               # base Runge-Kutta: 2 (RK2 of Table 1) or 3 (SSP-RK3)
+    m: int = 2                  # rate ratio
+    steps: int = 100
+    gamma: float = 1.4
+    prandtl: float = 0.72
+    mu_lower: float = 1e-3
+    mu_upper: float = 1e-3
+    gravity: float = 0.0
+    t_lower: float = 16.0       # fast domain: 4x sound speed
+    t_upper: float = 1.0
+    amplitude: float = 1e-2
+    width: float = 0.5
+    seed: int = 0
+    cfl: float = 0.5
+    dnum: float = 0.25
+    extra: dict = field(default_factory=dict, compare=False)
+
+    @property
+    def dx(self) -> float:
+        return self.lx / self.nx
+
+    @property
+    def dz_lower(self) -> float:
+        return self.lz_lower / self.nz_lower
+
+    @property
+    def dz_upper(self) -> float:
+        return self.lz_upper / self.nz_upper
+
+    @property
+    def s(self) -> int:
+        return self.base
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def small() -> Workload:
+    """64x32 cells per domain, MPRK with the RK2 base, m = 2, 100 slow steps."""
+    return Workload("two-domain 2D CNS 64x32 x2, MPRK2 m=2", nx=64, nz_lower=32, nz_upper=32,
+                    base=2, m=2, steps=100, n_buffer=4, seed=0)
+
+
+def large() -> Workload:
+    """1024x512 cells per domain, 4 buffer rows, SSP-RK3 base, m = 4, 1000 slow steps."""
+    return Workload("two-domain 2D CNS 1024x512 x2, MPRK3 m=4", nx=1024, nz_lower=512,
+                    nz_upper=512, base=3, m=4, steps=1000, n_buffer=4, seed=1)
+
+
+def centre(w: Workload):
+    rng = np.random.default_rng(w.seed)
+    xc = rng.uniform(-w.lx / 2, w.lx / 2)
+    zc = rng.uniform(-0.7 * w.lz_lower, 0.7 * w.lz_upper)
+    return float(xc), float(zc)
+
+
+def _domain(w: Workload, lower: bool, xc: float, zc: float) -> np.ndarray:
+    nz = w.nz_lower if lower else w.nz_upper
+    dz = w.dz_lower if lower else w.dz_upper
+    z0 = -w.lz_lower if lower else 0.0
+    T = w.t_lower if lower else w.t_upper
+    g = w.gamma
+    p0 = 1.0 / g
+    rho0 = g * p0 / T
+    x = -w.lx / 2 + (np.arange(w.nx) + 0.5) * w.dx
+    z = z0 + (np.arange(nz) + 0.5) * dz
+    ddx = np.abs(x - xc)
+    ddx = np.minimum(ddx, w.lx - ddx)
+    r2 = ddx[None, :] ** 2 + (z[:, None] - zc) ** 2
+    p = p0 * (1.0 + w.amplitude * np.exp(-r2 / w.width ** 2))
+    rho = rho0 * (p / p0) ** (1.0 / g)
+    q = np.zeros((4, nz, w.nx))
+    q[0] = rho
+    q[3] = p / (g - 1.0)
+    return q
+
+
+def initial_state(w: Workload):
+    """(q_lower, q_upper) as float64 numpy arrays."""
+    xc, zc = centre(w)
+    return _domain(w, True, xc, zc), _domain(w, False, xc, zc)
+
+
+def random_state(w: Workload, seed: int, amp: float = 0.05):
+    """Random smooth-free physical states (used for small brute-force checks):
+    rho, T within +-amp relative of the background, |u|, |w| <= amp * a."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for lower in (True, False):
+        nz = w.nz_lower if lower else w.nz_upper
+        T0 = w.t_lower if lower else w.t_upper
+        g = w.gamma
+        rho0 = 1.0 / T0
+        rho = rho0 * (1 + amp * rng.uniform(-1, 1, (nz, w.nx)))
+        T = T0 * (1 + amp * rng.uniform(-1, 1, (nz, w.nx)))
+        a = np.sqrt(T)
+        u = amp * a * rng.uniform(-1, 1, (nz, w.nx))
+        v = amp * a * rng.uniform(-1, 1, (nz, w.nx))
+        p = rho * T / g
+        q = np.zeros((4, nz, w.nx))
+        q[0] = rho
+        q[1] = rho * u
+        q[2] = rho * v
+        q[3] = p / (g - 1) + 0.5 * rho * (u * u + v * v)
+        out.append(q)
+    return out[0], out[1]
+
+
+def uniform_state(w: Workload, rho: float, u: float, wv: float, p: float):
+    g = w.gamma
+    res = []
+    for nz in (w.nz_lower, w.nz_upper):
+        q = np.zeros((4, nz, w.nx))
+        q[0] = rho
+        q[1] = rho * u
+        q[2] = rho * wv
+        q[3] = p / (g - 1) + 0.5 * rho * (u * u + wv * wv)
+        res.append(q)
+    return res[0], res[1]
