@@ -1,0 +1,273 @@
+"""Benchmark: MPRK vs single-rate RK on two coupled 2D Navier-Stokes domains.
+
+One *step* is one slow step of the whole hot path (every stage launch of the
+MPRK schedule, with the device reductions every --check-every steps) on the
+1024x512-per-domain workload (SSP-RK3 base, m = 4, 4 buffer rows, FP64),
+inputs resident in HBM before timing starts.
+
+The JSON line reports MPRK cell-stage updates per second (cell-stage counts of
+Section 4: s N_S + m s (N_B + N_F) per slow step), per-step p50/p99 latency,
+the single-rate RK3 at the fast step dt/m on the same GPU, the errors of both
+against a fine single-rate reference (equal-accuracy comparison), the stage
+kernel's roofline position, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed slow steps (default: workload's 1000)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--latency-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def l2(dx, dzs, diffs):
+    """Per-component L2 norm weighted by cell size (Section 5 error norm)."""
+    out = np.zeros(4)
+    for d, dz in zip(diffs, dzs):
+        out += (d.astype(np.float64) ** 2).sum(axis=(1, 2)) * dx * dz
+    return np.sqrt(out)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mprk_kernels.hip", "mprk_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2202_11890_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per stage launch from a committed counter summary, if its
+    kernel-source hash matches the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_%s_hbm_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2202_11890_amd import costmodel, inputs, mprk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = inputs.large() if args.workload == "large" else inputs.small()
+    K = args.steps if args.steps is not None else w.steps
+    W = args.warmup
+    s, m = w.base, w.m
+    nzf = w.nz_lower if w.fast_is_lower else w.nz_upper
+    nzs = w.nz_upper if w.fast_is_lower else w.nz_lower
+    nF, nB, nS = costmodel.partition_counts(w.nx, nzf, nzs, w.n_buffer)
+    cs_step = costmodel.mprk_cell_stages(nF, nB, nS, m, s)
+    sr_cs_step = costmodel.sr_cell_stages(nF + nB + nS, m, s)
+    bytes_step = costmodel.algorithmic_bytes_per_step(nF, nB, nS, m, s)
+
+    ql0, qu0 = inputs.initial_state(w)
+    tl0 = torch.from_numpy(ql0).to(dev)
+    tu0 = torch.from_numpy(qu0).to(dev)
+    tl, tu = tl0.clone(), tu0.clone()
+    cfg = mprk.config_of_workload(w)
+    sol = mprk.Solver(cfg, tl, tu)
+    dt = sol.stable_dt(w.cfl, w.dnum)
+
+    # ---- warm-up, then restore the initial state
+    sol.run(dt, max(W, 1), check_every=0)
+    tl.copy_(tl0)
+    tu.copy_(tu0)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K slow steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sol.run(dt, K, check_every=args.check_every)
+    torch.cuda.synchronize()
+    t_mprk = time.perf_counter() - t0
+    ms_step = 1e3 * t_mprk / K
+    value = cs_step * K / t_mprk
+    mprk_final = (tl.cpu().numpy(), tu.cpu().numpy())
+    print("# mprk: %d steps in %.3f s (%.1f us/step), status %d" %
+          (K, t_mprk, 1e6 * t_mprk / K, st["status"]), file=sys.stderr, flush=True)
+
+    # ---- per-step latency (events on the solver's stream)
+    lat = []
+    stream = sol.stream
+    for _ in range(args.latency_steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sol.step(dt)
+        e1.record(stream)
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+
+    # ---- stage-kernel time per launch (events around each launch)
+    sol.profile(True)
+    for _ in range(args.profile_steps):
+        sol.step(dt)
+    k_ms, k_n = sol.profile_take()
+    sol.profile(False)
+    avg_launch_s = k_ms * 1e-3 / k_n
+    launches_per_step = m * s
+    bytes_per_launch = bytes_step / launches_per_step
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = traffic_from_profiles(args.workload)
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "stage_kernel",
+        "avg_launch_us": round(avg_launch_s * 1e6, 3),
+        "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        "kernel_time_per_step_us": round(avg_launch_s * launches_per_step * 1e6, 2),
+    }
+    print("# stage kernel: %.2f us/launch, %.0f GB/s algorithmic" %
+          (avg_launch_s * 1e6, achieved), file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "cell-stage updates/s, MPRK vs single-rate RK at equal error; p50/p99 latency",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "nx": w.nx, "nz_lower": w.nz_lower, "nz_upper": w.nz_upper,
+            "base": "SSP-RK3" if s == 3 else "RK2", "m": m, "n_buffer": w.n_buffer,
+            "dt": dt, "cfl": w.cfl, "diffusion_number": w.dnum,
+            "check_every": args.check_every,
+            "cell_stages_per_step": cs_step,
+            "parallelism": "single GPU",
+        },
+        "latency_ms_per_step": {"p50": float(np.percentile(lat_ms, 50)),
+                                "p99": float(np.percentile(lat_ms, 99)),
+                                "n": int(lat_ms.size)},
+        "sr_equivalent_rate": sr_cs_step * K / t_mprk,
+        "model_speedup": costmodel.speedup_from_counts(nF, nB, nS, m, s),
+        "roofline": roofline,
+    }
+    sol.close()
+
+    # ---- single-rate RK at the fast step on the same GPU
+    if not args.no_sr:
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        sr = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu)
+        sr.run(dt / m, 2, check_every=0)
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sst = sr.run(dt / m, K * m, check_every=args.check_every * m)
+        torch.cuda.synchronize()
+        t_sr = time.perf_counter() - t0
+        sr_final = (tl.cpu().numpy(), tu.cpu().numpy())
+        sr.close()
+        out["single_rate"] = {
+            "method": "SSP-RK3" if s == 3 else "RK2", "dt": dt / m, "steps": K * m,
+            "value": sr_cs_step * K / t_sr, "seconds": t_sr, "status": sst["status"],
+            "time_to_solution_speedup": t_sr / t_mprk,
+        }
+        print("# single rate: %.3f s, speedup %.3f" % (t_sr, t_sr / t_mprk), file=sys.stderr,
+              flush=True)
+
+        # ---- equal-accuracy check against a fine single-rate reference
+        if not args.no_accuracy:
+            nref = 8
+            tl.copy_(tl0)
+            tu.copy_(tu0)
+            ref = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu)
+            ref.run(dt / (m * nref), K * m * nref, check_every=K * m)
+            torch.cuda.synchronize()
+            rf = (tl.cpu().numpy(), tu.cpu().numpy())
+            ref.close()
+            dzs = (w.dz_lower, w.dz_upper)
+            e_mprk = l2(w.dx, dzs, [mprk_final[0] - rf[0], mprk_final[1] - rf[1]])
+            e_sr = l2(w.dx, dzs, [sr_final[0] - rf[0], sr_final[1] - rf[1]])
+            out["equal_accuracy"] = {
+                "reference": "single-rate %s at dt/%d" % ("SSP-RK3" if s == 3 else "RK2", m * nref),
+                "t_end": K * dt,
+                "l2_mprk": [float(x) for x in e_mprk],
+                "l2_single_rate": [float(x) for x in e_sr],
+                "components": ["rho", "rho u", "rho w", "rho E"],
+            }
+
+    # ---- CPU oracle on a bounded sample (test infrastructure, host cores)
+    if not args.no_cpu:
+        import oracle
+
+        pb = oracle.Problem(w.nx, w.nz_lower, w.nz_upper, w.dx, w.dz_lower, w.dz_upper,
+                            fast_is_lower=w.fast_is_lower, n_buffer=w.n_buffer, gamma=w.gamma,
+                            prandtl=w.prandtl, mu_lower=w.mu_lower, mu_upper=w.mu_upper,
+                            gravity=w.gravity)
+        a, b = ql0.copy(), qu0.copy()
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.mprk_step(pb, s, m, dt, a, b)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or n >= K:
+                break
+        out["cpu_baseline"] = {
+            "value": cs_step * n / el, "unit": "cell-stage updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d slow steps of the same workload from its initial state (%.1f s)" % (n, el),
+        }
+        print("# cpu oracle: %d steps in %.1f s on %d threads" % (n, el, oracle.threads()),
+              file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

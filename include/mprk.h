@@ -1,0 +1,188 @@
+/*
+ * mprk.h -- C ABI of the MI355X (gfx950) multirate partitioned Runge-Kutta
+ * (MPRK) library for two vertically stacked compressible Navier-Stokes
+ * domains coupled through a rigid lid.
+ *
+ * Paper: Kang et al., "Multirate partitioned Runge-Kutta methods for coupled
+ * Navier-Stokes equations" (arXiv 2202.11890).
+ *
+ * What it computes
+ *   The coupled semi-discrete system of Section 3, eq.
+ *   (semi-discretized-coupled-model): dq^F/dt = R^F(q^F, q^B),
+ *   dq^B/dt = R^B(q^B, q^F, q^S), dq^S/dt = R^S(q^S, q^B), where F is the
+ *   fast domain, B the n_buffer slow rows next to the interface Gamma and S
+ *   the remaining slow rows.  R is the cell-centred second-order finite-volume
+ *   RHS of Section 2.1 and Appendix B (local Lax-Friedrichs inviscid flux with
+ *   a Roe-average wave speed, common-value viscous flux, bulk-coefficient
+ *   coupling at Gamma, eq. bulk-flux), restricted to the x-z plane.
+ *   Time integration is the MPRK method of eq. (MRK2) with the stage
+ *   schedule of Algorithm 1: the fast domain takes m substeps of dt/m, the
+ *   buffer restarts from q^B_n at each substep with the full step and is
+ *   averaged, the slow region takes one base step whose s stage values are
+ *   reused at every substep.
+ *
+ * Data layout (device memory, caller-owned)
+ *   q_lower, q_upper: float64 [4][nz][nx], x fastest, row 0 at the bottom,
+ *   components (rho, rho u, rho w, rho E), nondimensional (Appendix A).
+ *   Gamma lies between q_lower row nz_lower-1 and q_upper row 0.  x is
+ *   periodic; the bottom of the lower domain and the top of the upper domain
+ *   are slip adiabatic walls.
+ *
+ * Ownership and threading
+ *   State, workspace and stream belong to the caller; the library never calls
+ *   hipMalloc or hipFree.  Its device footprint is exactly the two state
+ *   arrays plus mprk_workspace_bytes().  mprk_step and mprk_run update the
+ *   state in place, asynchronously on the context's stream.  A context is not
+ *   thread-safe; calls on one context must not overlap.
+ *
+ * Errors
+ *   Every function returns MPRK_OK (0) or a negative mprk_status; nothing
+ *   throws across the ABI.  Kernel launches are asynchronous: a state that
+ *   becomes non-finite or non-physical is reported at the next check
+ *   (mprk_run's check points, mprk_diagnostics) as MPRK_ENONFINITE.
+ */
+#ifndef MPRK_H
+#define MPRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPRK_ABI_VERSION 1
+
+enum mprk_status {
+    MPRK_OK = 0,
+    MPRK_EINVAL = -1,       /* invalid configuration or argument                    */
+    MPRK_EBUFFER = -2,      /* n_buffer < 2s-1 while strict_buffer is set           */
+    MPRK_EWORKSPACE = -3,   /* workspace missing, too small or not 256-B aligned     */
+    MPRK_EHIP = -4,         /* a HIP runtime call or kernel launch failed            */
+    MPRK_ENONFINITE = -5,   /* non-finite value, rho <= 0 or p <= 0 detected         */
+    MPRK_EUNSUPPORTED = -6  /* valid request this build does not implement           */
+};
+
+/* Regions of eq. (semi-discretized-coupled-model), as bits. */
+enum mprk_region {
+    MPRK_REGION_F = 1,
+    MPRK_REGION_B = 2,
+    MPRK_REGION_S = 4,
+    MPRK_REGION_ALL = 7
+};
+
+typedef struct mprk_config {
+    int32_t abi_version;    /* must be MPRK_ABI_VERSION                              */
+    int32_t dim;            /* 2 (x-z plane); 3 is reserved                          */
+    int32_t nx, ny;         /* cells in x (periodic); ny must be 1 when dim == 2     */
+    int32_t nz_lower;       /* rows of the lower domain                              */
+    int32_t nz_upper;       /* rows of the upper domain                              */
+    double dx, dy;          /* cell sizes in x (and y); dy is ignored in 2D          */
+    double dz_lower;        /* cell height of the lower domain                       */
+    double dz_upper;        /* cell height of the upper domain                       */
+    int32_t fast_is_lower;  /* 1: the lower domain is F; 0: the upper domain is F    */
+    int32_t n_buffer;       /* slow rows next to Gamma forming B, 1..nz_slow-2       */
+    int32_t base_rk;        /* 2: two-stage RK2 of Table 1; 3: three-stage SSP-RK3   */
+    int32_t m;              /* rate ratio >= 1; m == 1 is the single-rate base method */
+    double gamma;           /* ratio of specific heats (> 1)                         */
+    double prandtl;         /* Prandtl number (> 0)                                  */
+    double mu_lower;        /* nondimensional viscosity of the lower domain (> 0)    */
+    double mu_upper;        /* nondimensional viscosity of the upper domain (> 0)    */
+    double gravity;         /* signed vertical gravity; source (0, 0, rho g, rho w g) */
+    int32_t flux_bits;      /* 64: FP64 flux arithmetic (32 is reserved)             */
+    int32_t strict_buffer;  /* 1: reject n_buffer < 2s-1 with MPRK_EBUFFER           */
+} mprk_config;
+
+typedef struct mprk_stats {
+    double totals_lower[4]; /* sum of q |K| per component, lower domain (Sec. 5.1)    */
+    double totals_upper[4]; /* same, upper domain                                     */
+    double lambda_lower;    /* max over cells of sum_d (|u_d| + a) / d_d              */
+    double lambda_upper;
+    double courant_lower;   /* max over cells and directions of (|u_d| + a) / d_d     */
+    double courant_upper;   /* (dt times this is the paper's Courant number)          */
+    double visc_lower;      /* max over cells of max(4/3, gamma/Pr) mu/rho sum 1/d_d^2 */
+    double visc_upper;
+    int64_t steps_done;     /* slow steps taken by this context                        */
+    int32_t status;         /* 0: state physical; 1: non-finite / rho<=0 / p<=0 seen   */
+    int32_t reserved;
+} mprk_stats;
+
+typedef struct mprk_ctx mprk_ctx;
+
+/* Check a configuration on the host; no GPU needed.  Writes a NUL-terminated
+ * reason into msg (if msg != NULL and len > 0).  Returns MPRK_OK, MPRK_EINVAL,
+ * MPRK_EBUFFER (only with strict_buffer) or MPRK_EUNSUPPORTED.  A buffer
+ * shorter than 2s-1 rows is accepted without strict_buffer: the method then
+ * runs, but is not exactly conservative (Section 3, Remark 1). */
+int mprk_validate(const mprk_config* cfg, char* msg, size_t len);
+
+/* Device workspace bytes a context needs for cfg (0 if cfg is invalid).
+ * Host-only. */
+size_t mprk_workspace_bytes(const mprk_config* cfg);
+
+/* Create a context bound to caller-owned device memory.
+ *   q_lower, q_upper : device state arrays (layout above), updated in place
+ *                      by mprk_step / mprk_run.
+ *   workspace        : device memory of at least mprk_workspace_bytes(cfg)
+ *                      bytes, 256-byte aligned, owned by the caller and not
+ *                      touched by anyone else while the context lives.
+ *   hip_stream       : hipStream_t to launch on (NULL: the null stream).
+ * On success *out receives the context (host memory owned by the library,
+ * released by mprk_destroy). */
+int mprk_create(const mprk_config* cfg, double* q_lower, double* q_upper, void* workspace,
+                size_t workspace_bytes, void* hip_stream, mprk_ctx** out);
+
+/* Change the stream later launches go to. */
+int mprk_set_stream(mprk_ctx* ctx, void* hip_stream);
+
+/* One evaluation of the coupled RHS f(q) of eq. (semi-discretized-coupled-
+ * model) at the given device state (which need not be the context's state),
+ * written to r_lower / r_upper (same layout) on the rows of the regions in
+ * region_mask; other rows of r are not written.  Asynchronous. */
+int mprk_rhs(mprk_ctx* ctx, const double* q_lower, const double* q_upper, double* r_lower,
+             double* r_upper, int region_mask);
+
+/* One slow step of size dt (eq. MRK2, Algorithm 1): m*s stage launches on the
+ * context's stream; the state is updated in place.  Asynchronous. */
+int mprk_step(mprk_ctx* ctx, double dt);
+
+/* nsteps slow steps of size dt.  Every check_every steps (and after the last
+ * one) runs the device reductions and synchronises the stream; returns
+ * MPRK_ENONFINITE at the first check that sees a bad state.  check_every <= 0
+ * checks only after the last step.  If out != NULL it receives the stats of
+ * the last check. */
+int mprk_run(mprk_ctx* ctx, double dt, int64_t nsteps, int64_t check_every, mprk_stats* out);
+
+/* Device reductions on the context's current state (totals, stability
+ * measures, status); synchronises the stream.  Returns MPRK_ENONFINITE if the
+ * state is bad (out is still filled). */
+int mprk_diagnostics(mprk_ctx* ctx, mprk_stats* out);
+
+/* Stable slow step from stats (host-only).  Per domain the step limit is
+ * 1 / (lambda/cr + visc/dn) (advective and diffusive limits combined); the
+ * slow step is min(m * fast-domain limit, slow-domain limit).  Returns
+ * MPRK_ENONFINITE if st->status is set, MPRK_EINVAL for non-positive cr, dn
+ * or wave speeds. */
+int mprk_stable_dt(const mprk_config* cfg, const mprk_stats* st, double cr, double dn,
+                   double* dt_out);
+
+/* Kernel timing aid.  While enabled, every stage launch is bracketed by a
+ * pair of HIP events recorded on the context's stream (host-side event
+ * objects only; no device allocation).  mprk_profile_take waits for the
+ * recorded events and returns the summed stage-kernel time in milliseconds
+ * and the number of launches since the previous take (or since enabling).
+ * Disabling drops unread timings. */
+int mprk_profile_enable(mprk_ctx* ctx, int on);
+int mprk_profile_take(mprk_ctx* ctx, double* kernel_ms, int64_t* launches);
+
+/* Release the context (not the caller's memory).  Synchronises its stream. */
+int mprk_destroy(mprk_ctx* ctx);
+
+/* Static description of a status code. */
+const char* mprk_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPRK_H */

@@ -794,19 +794,28 @@ int orc_wave_measures(const orc_cfg* c, const double* qlo, const double* qup, do
 }
 
 /*
- * Step-size rule: fast step dt_f = min(cr / lam_F, dn / vis_F); slow step
- * dt = min(m dt_f, cr / lam_S, dn / vis_S).  Returns dt (0 on a bad state).
+ * Step-size rule.  Per domain the stable step is 1 / (lam/cr + vis/dn): the
+ * advective (Courant) and diffusive (viscous and heat-conduction) limits are
+ * combined, because the odd-even mode receives both as negative real
+ * eigenvalue contributions (upwind-type dissipation 2 lam, diffusion 4 vis),
+ * so their sum must stay inside the real-axis stability interval.  Fast
+ * step dt_f from the fast domain; slow step dt = min(m dt_f, slow-domain
+ * step).  Returns dt (0 on a bad state).
  */
+static double domain_step(double lam, double vis, double cr, double dn)
+{
+    return 1.0 / (lam / cr + vis / dn);
+}
+
 double orc_dt_rule(const orc_cfg* c, const double* qlo, const double* qup, int m, double cr,
                    double dn)
 {
     double lam[2], cour[2], vis[2];
     if (orc_wave_measures(c, qlo, qup, lam, cour, vis)) return 0.0;
     int f = c->fast_is_lower ? 0 : 1, sl = 1 - f;
-    double dtf = cr / lam[f];
-    if (vis[f] > 0.0 && dn / vis[f] < dtf) dtf = dn / vis[f];
+    double dtf = domain_step(lam[f], vis[f], cr, dn);
+    double dts = domain_step(lam[sl], vis[sl], cr, dn);
     double dt = m * dtf;
-    if (cr / lam[sl] < dt) dt = cr / lam[sl];
-    if (vis[sl] > 0.0 && dn / vis[sl] < dt) dt = dn / vis[sl];
+    if (dts < dt) dt = dts;
     return dt;
 }

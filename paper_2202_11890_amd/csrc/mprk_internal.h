@@ -1,0 +1,93 @@
+// mprk_internal.h -- launch parameters shared by the host layer and the HIP
+// kernels of the MPRK library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mprk {
+
+constexpr int NV = 4;          // (rho, rho u, rho w, rho E)
+
+// Stage tile: TX columns x TZ rows of cells per workgroup of NT threads; each
+// thread owns a vertical pair of cells.  The conserved state is staged with a
+// 2-cell halo (reconstruction stencil), primitives with a 1-cell halo.
+constexpr int TX = 32;
+constexpr int TZ = 16;
+constexpr int NT = 256;
+constexpr int HX = TX + 4;
+constexpr int HZ = TZ + 4;
+constexpr int PX = TX + 2;
+constexpr int PZ = TZ + 2;
+
+// What a stage launch writes for a cell.
+enum Mode : int32_t {
+    MODE_RHS = 0,        // out = R
+    MODE_STAGE = 1,      // out = U + inc, inc = beta (Qin - U) + beta h R
+                         // (= alpha U + beta (Qin + h R), alpha + beta = 1)
+    MODE_ACC_FIRST = 2,  // acc = inc
+    MODE_ACC_ADD = 3,    // acc += inc
+    MODE_ACC_FINAL = 4,  // out = U + (acc + inc) / m
+};
+
+struct Combine {
+    double alpha;   // weight of the substep base U
+    double beta;    // weight of the stage input Qin (1 - alpha)
+    double bh;      // beta * step
+    int32_t mode;
+    int32_t pad;
+};
+
+struct DomainArgs {
+    const double* qin;     // stage value read by the stencil [NV][nz][nx]
+    const double* base;    // substep base U (pointwise)
+    double* out;           // destination of MODE_RHS / STAGE / ACC_FINAL
+    double* acc;           // buffer accumulator [NV][b_hi-b_lo][nx]
+    const double* ret_in;  // retained slow rows [NV][2][nx], read for rows outside
+                           // [b_lo, b_hi) when use_ret is set
+    double* ret_out;       // if set: save Qin rows [ret_lo, ret_lo+2) here
+    int32_t nz;
+    int32_t row_lo, row_hi;  // rows computed by this launch
+    int32_t b_lo, b_hi;      // buffer rows (empty range: none)
+    int32_t ret_lo;          // first of the two retained slow rows next to B
+    int32_t use_ret;
+    int32_t gamma_top;       // 1: the interface is above the top row
+    int32_t gamma_bot;       // 1: the interface is below row 0
+    int32_t tiles_x, tiles_z, ntiles;
+    double dz, inv_dz;
+    double mu, kappa;
+    Combine main;            // rows outside [b_lo, b_hi)
+    Combine buf;             // rows inside  [b_lo, b_hi)
+};
+
+struct StageArgs {
+    DomainArgs d[2];         // 0 = lower, 1 = upper
+    int32_t nx;
+    int32_t nblocks;         // d[0].ntiles + d[1].ntiles
+    double dx, inv_dx;
+    double gamma, gm1, gravity;
+    double bu, bT;           // bulk coefficients of the interface flux
+    double half_dz1_mu1;     // dz_lower / (2 mu_lower): wall velocity u_w1 = u1 + sigma * this
+    double inv_m;
+};
+
+// Reductions: per-domain fields.
+constexpr int RED_BLOCKS = 256;   // partial blocks per domain
+constexpr int RED_THREADS = 256;
+constexpr int RED_FIELDS = 12;    // sum[4], comp[4], lambda, courant, visc, bad
+
+struct ReduceArgs {
+    const double* q[2];
+    int32_t nz[2];
+    int32_t nx;
+    double inv_dx, inv_dz[2];
+    double visc_coef[2];     // max(4/3, gamma/Pr) * mu_d * (1/dx^2 + 1/dz_d^2)
+    double gamma, gm1;
+    double* partial;         // [2][RED_BLOCKS][RED_FIELDS]
+    double* final_;          // [2][RED_FIELDS]
+};
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+
+}  // namespace mprk

@@ -1,0 +1,533 @@
+// mprk_kernels.hip -- gfx950 kernels of the MPRK library.
+//
+// stage_kernel: one MPRK stage for every cell a launch covers, in both
+// domains at once.  For each cell: the coupled finite-volume RHS (Section 2.1,
+// Appendix B restricted to x-z; local Lax-Friedrichs flux with Roe-average
+// wave speed, common-value viscous flux, bulk-coefficient interface flux of
+// eq. bulk-flux) and the stage combination of its partition (eq. MRK2 in a
+// low-storage substep form).
+//
+// Tiling: a workgroup of 256 threads owns a 32 x 16 tile of one domain.  The
+// tile's conserved state (2-cell halo) and primitives u, w, T (1-cell halo)
+// are staged in LDS; every face of the tile is computed exactly once (two
+// faces per cell plus one left column and one bottom row of edge faces) by a
+// single direction-generic face routine; the fluxes are exchanged through LDS
+// (aliasing the staged state) and each thread forms the divergence of its
+// two cells.
+//
+// reduce_*: deterministic (fixed-order) device reductions for the totals,
+// stability measures and the physical-state flag.
+#include "mprk_internal.h"
+
+namespace mprk {
+
+namespace {
+
+constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
+constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
+constexpr int LDS_G = 2 * TX;              // u, T of the cell across the interface
+constexpr int LDS_O = NV * TX;             // conserved state of that cell
+constexpr int LDS_EX = NV * TZ * (TX + 1) + NV * (TZ + 1) * TX;  // face fluxes
+constexpr int LDS_N = LDS_Q + LDS_P + LDS_G + LDS_O;
+static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
+
+__device__ __forceinline__ int wrapx(int c, int nx)
+{
+    int r = c % nx;
+    return r < 0 ? r + nx : r;
+}
+
+// Cell primitives.  Contraction is off so that the value is identical
+// wherever it is evaluated: the interface flux is computed on both sides of
+// the interface and must agree to the bit for conservation.
+__device__ __forceinline__ void primitives(double rho, double mx, double mz, double en,
+                                           double gamma, double gm1, double& u, double& w,
+                                           double& T)
+{
+#pragma clang fp contract(off)
+    double ir = 1.0 / rho;
+    u = mx * ir;
+    w = mz * ir;
+    double p = gm1 * (en - 0.5 * (mx * u + mz * w));
+    T = gamma * p * ir;
+}
+
+// Interface viscous flux in +z (Appendix B, eq. bulk-flux; hat w = 0 and
+// hat sigma_zz = 0 on the lid): (0, sigma_xz, 0, u_w sigma_xz - Pi_z) with
+// sigma_xz = b_u (u2 - u1), Pi_z = -b_T (T2 - T1), u_w = u1 + sigma dz1/(2 mu1).
+// Index 1 is the lower cell, 2 the upper cell.  Contraction off: both domains
+// evaluate it and must obtain the same bits.
+__device__ __forceinline__ void interface_flux(const StageArgs& A, double u1, double T1,
+                                               double u2, double T2, double& f1, double& f3)
+{
+#pragma clang fp contract(off)
+    double sig = A.bu * (u2 - u1);
+    double pi = -A.bT * (T2 - T1);
+    double uw = u1 + sig * A.half_dz1_mu1;
+    f1 = sig;
+    f3 = uw * sig - pi;
+}
+
+struct Lds {
+    double* q;   // [NV][HZ][HX]
+    double* p;   // [3][PZ][PX]
+    double* g;   // [2][TX]
+    double* o;   // [NV][TX]
+};
+
+__device__ __forceinline__ int qidx(int v, int r, int c) { return (v * HZ + r + 2) * HX + c + 2; }
+__device__ __forceinline__ int pidx(int f, int r, int c) { return (f * PZ + r + 1) * PX + c + 1; }
+
+// Boundary kinds of a face.
+enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
+
+// Numerical flux (inviscid minus viscous) through the face between tile cell
+// (c, r) and its +dir neighbour, in the face-normal frame: returns
+// (F_rho, F_normal-momentum, F_tangential-momentum, F_energy).
+//   kind FACE_TOP:    (c, r) is the top interior row; the other side is its
+//                     mirror; gam = interface above.
+//   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; gam = interface
+//                     below.
+// For a wall the viscous flux is zero; at the interface it is the bulk flux.
+template <int DOM>
+__device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& D, const Lds& L,
+                                          int dir, int c, int r, int kind, double F[NV])
+{
+    const double gamma = A.gamma, gm1 = A.gm1;
+    const int sn = dir ? HX : 1;             // normal stride in the state tile
+    const int vn = dir ? 2 : 1;              // normal momentum component
+    const int vt = dir ? 1 : 2;              // tangential momentum component
+    const int base = qidx(0, r, c);
+    const int plane = HZ * HX;
+
+    // Reconstruction of conserved variables with central cell gradients:
+    // qL = q_c + (q_{c+1} - q_{c-1})/4, qR = q_{c+1} - (q_{c+2} - q_c)/4.
+    double qL[NV], qR[NV];
+    {
+        const int comp[NV] = {0, vn, vt, 3};
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double* s = L.q + comp[k] * plane + base;
+            double qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
+            qL[k] = q0 + 0.25 * (q1 - qm);
+            qR[k] = q1 - 0.25 * (q2 - q0);
+        }
+    }
+    if (kind == FACE_TOP) {
+        qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3];
+    } else if (kind == FACE_BOTTOM) {
+        qL[0] = qR[0]; qL[1] = -qR[1]; qL[2] = qR[2]; qL[3] = qR[3];
+    }
+
+    // Local Lax-Friedrichs flux, lambda = max(|u_n| + a) over qL, qR and the
+    // Roe average (sqrt(rho)-weighted velocity and total enthalpy).
+    const double rL = 1.0 / qL[0], rR = 1.0 / qR[0];
+    const double unL = qL[1] * rL, utL = qL[2] * rL;
+    const double unR = qR[1] * rR, utR = qR[2] * rR;
+    const double pL = gm1 * (qL[3] - 0.5 * (qL[1] * unL + qL[2] * utL));
+    const double pR = gm1 * (qR[3] - 0.5 * (qR[1] * unR + qR[2] * utR));
+    const double aL = sqrt(gamma * pL * rL);
+    const double aR = sqrt(gamma * pR * rR);
+    const double sL = sqrt(qL[0]), sR = sqrt(qR[0]);
+    const double iw = 1.0 / (sL + sR);
+    const double unr = (sL * unL + sR * unR) * iw;
+    const double utr = (sL * utL + sR * utR) * iw;
+    const double HL = (qL[3] + pL) * rL, HR = (qR[3] + pR) * rR;
+    const double Hr = (sL * HL + sR * HR) * iw;
+    const double ar = sqrt(gm1 * (Hr - 0.5 * (unr * unr + utr * utr)));
+    const double lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
+    const double hl = 0.5 * lam;
+    F[0] = 0.5 * (qL[1] + qR[1]) - hl * (qR[0] - qL[0]);
+    F[1] = 0.5 * (qL[1] * unL + qR[1] * unR + pL + pR) - hl * (qR[1] - qL[1]);
+    F[2] = 0.5 * (qL[2] * unL + qR[2] * unR) - hl * (qR[2] - qL[2]);
+    F[3] = 0.5 * ((qL[3] + pL) * unL + (qR[3] + pR) * unR) - hl * (qR[3] - qL[3]);
+
+    if (kind == FACE_INTERIOR) {
+        // Common values: averaged velocity, normal derivative by finite
+        // difference, tangential derivative by averaging cell gradients.
+        const int pb = pidx(0, r, c);
+        const int pn = dir ? PX : 1;
+        const int pt = dir ? 1 : PX;
+        const int fn = dir ? 1 : 0;          // normal velocity in the primitive tile
+        const int ft = dir ? 0 : 1;
+        const int pp = PZ * PX;
+        const double* Un = L.p + fn * pp + pb;
+        const double* Ut = L.p + ft * pp + pb;
+        const double* Tt = L.p + 2 * pp + pb;
+        const double inv_n = dir ? D.inv_dz : A.inv_dx;
+        const double inv_t4 = 0.25 * (dir ? A.inv_dx : D.inv_dz);
+        const double unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
+        const double dn_un = (unB - unA) * inv_n;
+        const double dn_ut = (utB - utA) * inv_n;
+        const double dn_T = (Tt[pn] - Tt[0]) * inv_n;
+        const double dt_un = (Un[pt] - Un[-pt] + Un[pn + pt] - Un[pn - pt]) * inv_t4;
+        const double dt_ut = (Ut[pt] - Ut[-pt] + Ut[pn + pt] - Ut[pn - pt]) * inv_t4;
+        const double mu = D.mu;
+        const double snn = mu * ((4.0 / 3.0) * dn_un - (2.0 / 3.0) * dt_ut);
+        const double snt = mu * (dn_ut + dt_un);
+        F[1] -= snn;
+        F[2] -= snt;
+        F[3] -= 0.5 * (unA + unB) * snn + 0.5 * (utA + utB) * snt + D.kappa * dn_T;
+    } else {
+        const bool gam = (kind == FACE_TOP) ? D.gamma_top : D.gamma_bot;
+        if (gam) {
+            // Only z-faces reach here: normal = w, tangential = u.
+            double u1, T1, u2, T2;
+            if (DOM == 0) {   // interface above the lower domain's top row r
+                u1 = L.p[pidx(0, r, c)];
+                T1 = L.p[pidx(2, r, c)];
+                u2 = L.g[c];
+                T2 = L.g[TX + c];
+            } else {          // interface below the upper domain's bottom row r+1
+                u1 = L.g[c];
+                T1 = L.g[TX + c];
+                u2 = L.p[pidx(0, r + 1, c)];
+                T2 = L.p[pidx(2, r + 1, c)];
+            }
+            double f1, f3;
+            interface_flux(A, u1, T1, u2, T2, f1, f3);
+            F[2] -= f1;   // tangential momentum (x) component
+            F[3] -= f3;
+        }
+    }
+}
+
+struct FaceJob {
+    int dir, c, r, kind, valid;
+};
+
+template <int DOM>
+__device__ void stage_tile(const StageArgs& A, int tile, double* lds)
+{
+    const DomainArgs& D = A.d[DOM];
+    const DomainArgs& O = A.d[1 - DOM];
+    const int tid = threadIdx.x;
+    const int nx = A.nx, nz = D.nz;
+    const int tx = tile % D.tiles_x, tz = tile / D.tiles_x;
+    const int x0 = tx * TX;
+    const int z0 = D.row_lo + tz * TZ;
+    const int nrows = min(TZ, D.row_hi - z0);
+    const int ncols = min(TX, nx - x0);
+
+    Lds L;
+    L.q = lds;
+    L.p = lds + LDS_Q;
+    L.g = L.p + LDS_P;
+    L.o = L.g + LDS_G;
+    double* ex_x = lds;                          // [NV][TZ][TX+1]
+    double* ex_z = lds + NV * TZ * (TX + 1);     // [NV][TZ+1][TX]
+
+    const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + nrows == nz)
+                                      : (D.gamma_bot && z0 == 0);
+
+    // ---- stage the state tile (periodic in x, mirror rows beyond the domain)
+    for (int idx = tid; idx < LDS_Q; idx += NT) {
+        const int v = idx / (HZ * HX);
+        const int rem = idx - v * (HZ * HX);
+        const int zr = rem / HX;
+        const int xc = rem - zr * HX;
+        const int col = wrapx(x0 + xc - 2, nx);
+        int row = z0 + zr - 2;
+        bool mir = false;
+        if (row < 0) { row = 0; mir = true; }
+        else if (row >= nz) { row = nz - 1; mir = true; }
+        double val;
+        if (D.use_ret && (row < D.b_lo || row >= D.b_hi)) {
+            int rr = row - D.ret_lo;
+            rr = rr < 0 ? 0 : (rr > 1 ? 1 : rr);
+            val = D.ret_in[(size_t)(v * 2 + rr) * nx + col];
+        } else {
+            val = D.qin[((size_t)v * nz + row) * nx + col];
+        }
+        if (mir && v == 2) val = -val;
+        L.q[idx] = val;
+    }
+    if (has_gamma && tid < NV * TX) {
+        const int v = tid / TX, c = tid - v * TX;
+        const int col = wrapx(x0 + c, nx);
+        const int orow = (DOM == 0) ? 0 : O.nz - 1;
+        L.o[tid] = O.qin[((size_t)v * O.nz + orow) * nx + col];
+    }
+    __syncthreads();
+
+    // ---- primitives on the tile plus a 1-cell ring
+    for (int idx = tid; idx < PZ * PX; idx += NT) {
+        const int pr = idx / PX, pc = idx - pr * PX;
+        const int b = qidx(0, pr - 1, pc - 1);
+        double u, w, T;
+        primitives(L.q[b], L.q[b + HZ * HX], L.q[b + 2 * HZ * HX], L.q[b + 3 * HZ * HX],
+                   A.gamma, A.gm1, u, w, T);
+        L.p[idx] = u;
+        L.p[PZ * PX + idx] = w;
+        L.p[2 * PZ * PX + idx] = T;
+    }
+    if (has_gamma && tid < TX) {
+        double u, w, T;
+        primitives(L.o[tid], L.o[TX + tid], L.o[2 * TX + tid], L.o[3 * TX + tid], A.gamma,
+                   A.gm1, u, w, T);
+        L.g[tid] = u;
+        L.g[TX + tid] = T;
+    }
+    __syncthreads();
+
+    // ---- faces: slots 0,1 = x-faces right of the two cells, 2,3 = z-faces
+    // above them, 4 = tile-edge faces (left column, bottom row) in wave 0.
+    const int c = tid % TX;
+    const int r0 = 2 * (tid / TX);
+    const bool ok0 = (c < ncols) && (r0 < nrows);
+    const bool ok1 = (c < ncols) && (r0 + 1 < nrows);
+
+    double qc[2][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        qc[0][v] = L.q[qidx(v, r0, c)];
+        qc[1][v] = L.q[qidx(v, r0 + 1, c)];
+    }
+
+    FaceJob job[5];
+    job[0] = {0, c, r0, FACE_INTERIOR, ok0};
+    job[1] = {0, c, r0 + 1, FACE_INTERIOR, ok1};
+    job[2] = {1, c, r0, (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR, ok0};
+    job[3] = {1, c, r0 + 1, (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR, ok1};
+    if (tid < TZ) {
+        job[4] = {0, -1, tid, FACE_INTERIOR, tid < nrows};
+    } else if (tid < TZ + TX) {
+        const int cc = tid - TZ;
+        job[4] = {1, cc, -1, (z0 == 0) ? FACE_BOTTOM : FACE_INTERIOR, cc < ncols};
+    } else {
+        job[4] = {0, 0, 0, FACE_INTERIOR, 0};
+    }
+
+    double F[5][NV];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        if (job[j].valid) face_flux<DOM>(A, D, L, job[j].dir, job[j].c, job[j].r, job[j].kind, F[j]);
+    }
+    __syncthreads();   // all LDS reads of the staged state are done
+
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        if (!job[j].valid) continue;
+        const int dir = job[j].dir;
+        // Back from the face-normal frame to (rho, rho u, rho w, rho E).
+        const double g1 = dir ? F[j][2] : F[j][1];
+        const double g2 = dir ? F[j][1] : F[j][2];
+        double* e;
+        int stride;
+        if (dir == 0) {
+            e = ex_x + job[j].r * (TX + 1) + job[j].c + 1;
+            stride = TZ * (TX + 1);
+        } else {
+            e = ex_z + (job[j].r + 1) * TX + job[j].c;
+            stride = (TZ + 1) * TX;
+        }
+        e[0] = F[j][0];
+        e[stride] = g1;
+        e[2 * stride] = g2;
+        e[3 * stride] = F[j][3];
+    }
+    __syncthreads();
+
+    // ---- divergence, source and stage combination
+    const int col = x0 + c;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const bool ok = h ? ok1 : ok0;
+        if (!ok) continue;
+        const int r = r0 + h;
+        const int row = z0 + r;
+        double R[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double* fx = ex_x + v * TZ * (TX + 1) + r * (TX + 1) + c;
+            const double* fz = ex_z + v * (TZ + 1) * TX + r * TX + c;
+            R[v] = -(fx[1] - fx[0]) * A.inv_dx - (fz[TX] - fz[0]) * D.inv_dz;
+        }
+        R[2] += qc[h][0] * A.gravity;
+        R[3] += qc[h][2] * A.gravity;
+
+        const bool inb = (row >= D.b_lo && row < D.b_hi);
+        const Combine cb = inb ? D.buf : D.main;
+        const size_t plane = (size_t)nz * nx;
+        const size_t id = (size_t)row * nx + col;
+        if (cb.mode == MODE_RHS) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) D.out[v * plane + id] = R[v];
+        } else if (cb.alpha == 0.0) {
+            // First stage of a base step: Qin is the base U itself.
+#pragma unroll
+            for (int v = 0; v < NV; ++v) D.out[v * plane + id] = qc[h][v] + cb.bh * R[v];
+        } else {
+            // Increment form of alpha U + beta (Qin + h R): U + beta (Qin - U)
+            // + beta h R, exact when R = 0 and Qin = U.
+            double U[NV], inc[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                U[v] = D.base[v * plane + id];
+                inc[v] = cb.beta * (qc[h][v] - U[v]) + cb.bh * R[v];
+            }
+            if (cb.mode == MODE_STAGE) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) D.out[v * plane + id] = U[v] + inc[v];
+            } else {
+                // Buffer: accumulate the increments of the m trial steps and
+                // add their mean to q^B_n after the last one.
+                const size_t nb = (size_t)(D.b_hi - D.b_lo);
+                const size_t ia = (size_t)(row - D.b_lo) * nx + col;
+                if (cb.mode == MODE_ACC_FIRST) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) D.acc[v * nb * nx + ia] = inc[v];
+                } else if (cb.mode == MODE_ACC_ADD) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) D.acc[v * nb * nx + ia] += inc[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        D.out[v * plane + id] = U[v] + (D.acc[v * nb * nx + ia] + inc[v]) * A.inv_m;
+                }
+            }
+        }
+        if (D.ret_out && row >= D.ret_lo && row < D.ret_lo + 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * nx + col] = qc[h][v];
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void stage_kernel(const StageArgs A)
+{
+    __shared__ double lds[LDS_N];
+    const int b = blockIdx.x;
+    if (b < A.d[0].ntiles) stage_tile<0>(A, b, lds);
+    else stage_tile<1>(A, b - A.d[0].ntiles, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------
+struct RedVal {
+    double s[NV], e[NV];     // compensated sums: value + error term
+    double lam, cour, vis, bad;
+};
+
+__device__ __forceinline__ void two_sum(double& s, double& e, double x)
+{
+    const double t = s + x;
+    e += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+__device__ __forceinline__ void red_combine(RedVal& a, const RedVal& b)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        two_sum(a.s[v], a.e[v], b.s[v]);
+        a.e[v] += b.e[v];
+    }
+    a.lam = fmax(a.lam, b.lam);
+    a.cour = fmax(a.cour, b.cour);
+    a.vis = fmax(a.vis, b.vis);
+    a.bad = fmax(a.bad, b.bad);
+}
+
+__device__ __forceinline__ void red_store(double* p, const RedVal& a)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { p[v] = a.s[v]; p[NV + v] = a.e[v]; }
+    p[8] = a.lam; p[9] = a.cour; p[10] = a.vis; p[11] = a.bad;
+}
+
+__device__ __forceinline__ void red_load(const double* p, RedVal& a)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { a.s[v] = p[v]; a.e[v] = p[NV + v]; }
+    a.lam = p[8]; a.cour = p[9]; a.vis = p[10]; a.bad = p[11];
+}
+
+// Fixed-shape tree over the block: the result does not depend on timing.
+__device__ void block_tree(RedVal& mine, double* sh)
+{
+    const int tid = threadIdx.x;
+    red_store(sh + tid * RED_FIELDS, mine);
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            RedVal a, b;
+            red_load(sh + tid * RED_FIELDS, a);
+            red_load(sh + (tid + s) * RED_FIELDS, b);
+            red_combine(a, b);
+            red_store(sh + tid * RED_FIELDS, a);
+        }
+        __syncthreads();
+    }
+    red_load(sh, mine);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void reduce_partial(const ReduceArgs A)
+{
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    const int dom = blockIdx.y;
+    const double* q = A.q[dom];
+    const int n = A.nz[dom] * A.nx;
+    const double inv_dz = A.inv_dz[dom], vc = A.visc_coef[dom];
+    RedVal m;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { m.s[v] = 0.0; m.e[v] = 0.0; }
+    m.lam = m.cour = m.vis = m.bad = 0.0;
+    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+        const double rho = q[i], mx = q[(size_t)n + i], mz = q[2 * (size_t)n + i],
+                     en = q[3 * (size_t)n + i];
+        two_sum(m.s[0], m.e[0], rho);
+        two_sum(m.s[1], m.e[1], mx);
+        two_sum(m.s[2], m.e[2], mz);
+        two_sum(m.s[3], m.e[3], en);
+        const double ir = 1.0 / rho;
+        const double u = mx * ir, w = mz * ir;
+        const double p = A.gm1 * (en - 0.5 * (mx * u + mz * w));
+        const bool ok = (rho > 0.0) && (p > 0.0) && isfinite(mx) && isfinite(mz) && isfinite(en);
+        if (!ok) {
+            m.bad = 1.0;
+        } else {
+            const double a = sqrt(A.gamma * p * ir);
+            const double sx = (fabs(u) + a) * A.inv_dx;
+            const double sz = (fabs(w) + a) * inv_dz;
+            m.lam = fmax(m.lam, sx + sz);
+            m.cour = fmax(m.cour, fmax(sx, sz));
+            m.vis = fmax(m.vis, vc * ir);
+        }
+    }
+    block_tree(m, sh);
+    if (threadIdx.x == 0) red_store(A.partial + ((size_t)dom * RED_BLOCKS + blockIdx.x) * RED_FIELDS, m);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void reduce_final(const ReduceArgs A)
+{
+    static_assert(RED_BLOCKS == RED_THREADS, "one partial per thread");
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    const int dom = blockIdx.x;
+    RedVal m;
+    red_load(A.partial + ((size_t)dom * RED_BLOCKS + threadIdx.x) * RED_FIELDS, m);
+    block_tree(m, sh);
+    if (threadIdx.x == 0) red_store(A.final_ + (size_t)dom * RED_FIELDS, m);
+}
+
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t s)
+{
+    if (a.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_kernel, dim3(a.nblocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_partial, dim3(RED_BLOCKS, 2), dim3(RED_THREADS), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final, dim3(2), dim3(RED_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mprk

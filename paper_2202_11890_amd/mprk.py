@@ -1,0 +1,281 @@
+"""Python binding of the MPRK C ABI (``include/mprk.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libmprk.so`` built next to this file.  PyTorch supplies device
+memory and the HIP stream.  There is no fallback: if the library is missing
+or fails to load, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+ABI_VERSION = 1
+OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+REGION_F, REGION_B, REGION_S, REGION_ALL = 1, 2, 4, 7
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmprk.so")
+
+
+class mprk_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz_lower", ctypes.c_int32),
+        ("nz_upper", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dy", ctypes.c_double),
+        ("dz_lower", ctypes.c_double),
+        ("dz_upper", ctypes.c_double),
+        ("fast_is_lower", ctypes.c_int32),
+        ("n_buffer", ctypes.c_int32),
+        ("base_rk", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
+        ("mu_lower", ctypes.c_double),
+        ("mu_upper", ctypes.c_double),
+        ("gravity", ctypes.c_double),
+        ("flux_bits", ctypes.c_int32),
+        ("strict_buffer", ctypes.c_int32),
+    ]
+
+
+class mprk_stats(ctypes.Structure):
+    _fields_ = [
+        ("totals_lower", ctypes.c_double * 4),
+        ("totals_upper", ctypes.c_double * 4),
+        ("lambda_lower", ctypes.c_double),
+        ("lambda_upper", ctypes.c_double),
+        ("courant_lower", ctypes.c_double),
+        ("courant_upper", ctypes.c_double),
+        ("visc_lower", ctypes.c_double),
+        ("visc_upper", ctypes.c_double),
+        ("steps_done", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "totals_lower": list(self.totals_lower),
+            "totals_upper": list(self.totals_upper),
+            "lambda_lower": self.lambda_lower,
+            "lambda_upper": self.lambda_upper,
+            "courant_lower": self.courant_lower,
+            "courant_upper": self.courant_upper,
+            "visc_lower": self.visc_lower,
+            "visc_upper": self.visc_upper,
+            "steps_done": self.steps_done,
+            "status": self.status,
+        }
+
+
+EXPORTS = ("mprk_validate", "mprk_workspace_bytes", "mprk_create", "mprk_set_stream", "mprk_rhs",
+           "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_stable_dt", "mprk_profile_enable",
+           "mprk_profile_take", "mprk_destroy", "mprk_strerror")
+
+_lib = None
+
+
+class MprkError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, strerror(code), code))
+
+
+def load(path: str = LIB_PATH):
+    """Load libmprk.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    C = ctypes.POINTER(mprk_config)
+    S = ctypes.POINTER(mprk_stats)
+    V = ctypes.c_void_p
+    lib.mprk_validate.argtypes = [C, ctypes.c_char_p, ctypes.c_size_t]
+    lib.mprk_workspace_bytes.argtypes = [C]
+    lib.mprk_workspace_bytes.restype = ctypes.c_size_t
+    lib.mprk_create.argtypes = [C, V, V, V, ctypes.c_size_t, V, ctypes.POINTER(V)]
+    lib.mprk_set_stream.argtypes = [V, V]
+    lib.mprk_rhs.argtypes = [V, V, V, V, V, ctypes.c_int]
+    lib.mprk_step.argtypes = [V, ctypes.c_double]
+    lib.mprk_run.argtypes = [V, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, S]
+    lib.mprk_diagnostics.argtypes = [V, S]
+    lib.mprk_stable_dt.argtypes = [C, S, ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.mprk_profile_enable.argtypes = [V, ctypes.c_int]
+    lib.mprk_profile_take.argtypes = [V, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.mprk_destroy.argtypes = [V]
+    lib.mprk_strerror.argtypes = [ctypes.c_int]
+    lib.mprk_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().mprk_strerror(int(code)).decode()
+    except RuntimeError:
+        return "status %d" % code
+
+
+# ---- same-named thin wrappers ---------------------------------------------
+def mprk_validate(cfg: mprk_config):
+    buf = ctypes.create_string_buffer(256)
+    rc = load().mprk_validate(ctypes.byref(cfg), buf, 256)
+    return rc, buf.value.decode()
+
+
+def mprk_workspace_bytes(cfg: mprk_config) -> int:
+    return int(load().mprk_workspace_bytes(ctypes.byref(cfg)))
+
+
+def mprk_create(cfg, q_lower_ptr, q_upper_ptr, ws_ptr, ws_bytes, stream_ptr):
+    out = ctypes.c_void_p()
+    rc = load().mprk_create(ctypes.byref(cfg), q_lower_ptr, q_upper_ptr, ws_ptr, ws_bytes,
+                            stream_ptr, ctypes.byref(out))
+    return rc, out.value
+
+
+def mprk_rhs(ctx, ql, qu, rl, ru, mask):
+    return load().mprk_rhs(ctx, ql, qu, rl, ru, int(mask))
+
+
+def mprk_step(ctx, dt):
+    return load().mprk_step(ctx, float(dt))
+
+
+def mprk_run(ctx, dt, nsteps, check_every):
+    st = mprk_stats()
+    rc = load().mprk_run(ctx, float(dt), int(nsteps), int(check_every), ctypes.byref(st))
+    return rc, st
+
+
+def mprk_diagnostics(ctx):
+    st = mprk_stats()
+    rc = load().mprk_diagnostics(ctx, ctypes.byref(st))
+    return rc, st
+
+
+def mprk_stable_dt(cfg, st, cr, dn):
+    dt = ctypes.c_double()
+    rc = load().mprk_stable_dt(ctypes.byref(cfg), ctypes.byref(st), float(cr), float(dn),
+                               ctypes.byref(dt))
+    return rc, dt.value
+
+
+def mprk_profile_enable(ctx, on):
+    return load().mprk_profile_enable(ctx, int(bool(on)))
+
+
+def mprk_profile_take(ctx):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    rc = load().mprk_profile_take(ctx, ctypes.byref(ms), ctypes.byref(n))
+    return rc, ms.value, n.value
+
+
+def mprk_destroy(ctx):
+    return load().mprk_destroy(ctx)
+
+
+# ---- convenience ----------------------------------------------------------
+def config(nx, nz_lower, nz_upper, dx, dz_lower, dz_upper, *, fast_is_lower=True, n_buffer=4,
+           base_rk=2, m=2, gamma=1.4, prandtl=0.72, mu_lower=1e-3, mu_upper=1e-3, gravity=0.0,
+           flux_bits=64, strict_buffer=0, dim=2, ny=1, dy=0.0) -> mprk_config:
+    return mprk_config(ABI_VERSION, dim, nx, ny, nz_lower, nz_upper, dx, dy, dz_lower, dz_upper,
+                       int(bool(fast_is_lower)), n_buffer, base_rk, m, gamma, prandtl, mu_lower,
+                       mu_upper, gravity, flux_bits, strict_buffer)
+
+
+def config_of_workload(w, **over) -> mprk_config:
+    kw = dict(fast_is_lower=w.fast_is_lower, n_buffer=w.n_buffer, base_rk=w.base, m=w.m,
+              gamma=w.gamma, prandtl=w.prandtl, mu_lower=w.mu_lower, mu_upper=w.mu_upper,
+              gravity=w.gravity)
+    kw.update(over)
+    return config(w.nx, w.nz_lower, w.nz_upper, w.dx, w.dz_lower, w.dz_upper, **kw)
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise MprkError(rc, where)
+
+
+class Solver:
+    """Owns the workspace tensor and the context; the state tensors belong to
+    the caller and are updated in place."""
+
+    def __init__(self, cfg: mprk_config, q_lower, q_upper, stream=None):
+        import torch
+
+        for t in (q_lower, q_upper):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("state must be contiguous float64 device tensors")
+        if tuple(q_lower.shape) != (4, cfg.nz_lower, cfg.nx) or \
+                tuple(q_upper.shape) != (4, cfg.nz_upper, cfg.nx):
+            raise ValueError("state shapes do not match the configuration")
+        rc, msg = mprk_validate(cfg)
+        _check(rc, "mprk_validate: " + msg)
+        self.cfg = cfg
+        self.q_lower, self.q_upper = q_lower, q_upper
+        nbytes = mprk_workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=q_lower.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self._ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(q_lower.device)
+        rc, self.ctx = mprk_create(cfg, q_lower.data_ptr(), q_upper.data_ptr(), self._ws_ptr,
+                                   nbytes, self.stream.cuda_stream)
+        _check(rc, "mprk_create")
+
+    def rhs(self, q_lower, q_upper, r_lower, r_upper, mask=REGION_ALL):
+        _check(mprk_rhs(self.ctx, q_lower.data_ptr(), q_upper.data_ptr(), r_lower.data_ptr(),
+                        r_upper.data_ptr(), mask), "mprk_rhs")
+
+    def step(self, dt):
+        _check(mprk_step(self.ctx, dt), "mprk_step")
+
+    def run(self, dt, nsteps, check_every=0) -> dict:
+        rc, st = mprk_run(self.ctx, dt, nsteps, check_every)
+        _check(rc, "mprk_run")
+        return st.as_dict()
+
+    def diagnostics(self, check=True) -> dict:
+        rc, st = mprk_diagnostics(self.ctx)
+        if check:
+            _check(rc, "mprk_diagnostics")
+        return st.as_dict()
+
+    def stable_dt(self, cr=0.5, dn=0.25) -> float:
+        rc, st = mprk_diagnostics(self.ctx)
+        _check(rc, "mprk_diagnostics")
+        rc, dt = mprk_stable_dt(self.cfg, st, cr, dn)
+        _check(rc, "mprk_stable_dt")
+        return dt
+
+    def profile(self, on: bool):
+        _check(mprk_profile_enable(self.ctx, on), "mprk_profile_enable")
+
+    def profile_take(self):
+        """(summed stage-kernel milliseconds, launches) since the last take."""
+        rc, ms, n = mprk_profile_take(self.ctx)
+        _check(rc, "mprk_profile_take")
+        return ms, n
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mprk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
