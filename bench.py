@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run plain device copies of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -90,6 +92,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.large() if args.workload == "large" else inputs.small()
     K = args.steps if args.steps is not None else w.steps
     W = args.warmup
@@ -115,12 +125,17 @@ def main():
     tu.copy_(tu0)
     torch.cuda.synchronize()
 
-    # ---- timed region: K slow steps
+    # ---- timed region: K slow steps (wall clock and events on the stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(sol.stream)
     st = sol.run(dt, K, check_every=args.check_every)
+    ev1.record(sol.stream)
     torch.cuda.synchronize()
     t_mprk = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
     ms_step = 1e3 * t_mprk / K
     value = cs_step * K / t_mprk
     mprk_final = (tl.cpu().numpy(), tu.cpu().numpy())
@@ -140,17 +155,23 @@ def main():
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
 
-    # ---- stage-kernel time per launch (events around each launch)
+    # ---- stage-kernel time per launch.  Stage launches run back to back on
+    # the stream, so the event time of the timed region divided by the number
+    # of stage launches is the average launch duration (the reductions every
+    # check_every steps are included, about 1%).  Events bracketing every
+    # launch are also reported; they add a little overhead per launch.
     sol.profile(True)
     for _ in range(args.profile_steps):
         sol.step(dt)
     k_ms, k_n = sol.profile_take()
     sol.profile(False)
-    avg_launch_s = k_ms * 1e-3 / k_n
     launches_per_step = m * s
+    avg_launch_s = gpu_ms * 1e-3 / (K * launches_per_step)
     bytes_per_launch = bytes_step / launches_per_step
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic = traffic_from_profiles(args.workload)
+    if traffic is not None:
+        traffic = round(traffic / avg_launch_s / 1e9, 1)   # measured HBM GB/s
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -158,8 +179,10 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
+        "traffic_bytes_per_launch": traffic_from_profiles(args.workload),
         "kernel": "stage_kernel",
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
+        "avg_launch_us_bracketed": round(k_ms * 1e3 / k_n, 3),
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
         "kernel_time_per_step_us": round(avg_launch_s * launches_per_step * 1e6, 2),
     }

@@ -270,7 +270,7 @@ int mprk_destroy(mprk_ctx* c)
 {
     if (!c) return MPRK_EINVAL;
     hipError_t e = hipStreamSynchronize(c->stream);
-    for (hipEvent_t ev : c->prof_ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
     delete c;
     return e == hipSuccess ? MPRK_OK : MPRK_EHIP;
 }
@@ -337,6 +337,9 @@ Combine combine(double alpha, double h, int mode)
 int launch(mprk_ctx* c, StageArgs& a)
 {
     a.nblocks = a.d[0].ntiles + a.d[1].ntiles;
+    // Launches that cover only the buffer band of the slow domain put its
+    // (short) tiles first, so they run in the first wave of workgroups.
+    a.first = (a.d[c->slow].use_ret) ? c->slow : 0;
     if (!c->prof_on) return launch_stage(a, c->stream) == hipSuccess ? MPRK_OK : MPRK_EHIP;
     if (2 * c->prof_used + 2 > c->prof_ev.size()) {
         for (int i = 0; i < 2; ++i) {

@@ -9,12 +9,21 @@ namespace mprk {
 
 constexpr int NV = 4;          // (rho, rho u, rho w, rho E)
 
-// Stage tile: TX columns x TZ rows of cells per workgroup of NT threads; each
-// thread owns a vertical pair of cells.  The conserved state is staged with a
-// 2-cell halo (reconstruction stencil), primitives with a 1-cell halo.
-constexpr int TX = 32;
-constexpr int TZ = 16;
-constexpr int NT = 256;
+// Stage tile: TX columns x TZ rows of cells per workgroup of NT = TX*TZ/2
+// threads; each thread owns a vertical pair of cells.  The conserved state is
+// staged with a 2-cell halo (reconstruction stencil), primitives with a
+// 1-cell halo.
+#ifndef MPRK_TILE_X
+#define MPRK_TILE_X 32
+#endif
+#ifndef MPRK_TILE_Z
+#define MPRK_TILE_Z 16
+#endif
+constexpr int TX = MPRK_TILE_X;
+constexpr int TZ = MPRK_TILE_Z;
+constexpr int NT = TX * TZ / 2;
+static_assert(TZ % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
+static_assert(NT >= 64 + TX && TZ <= 64, "edge faces use waves 0 and 1");
 constexpr int HX = TX + 4;
 constexpr int HZ = TZ + 4;
 constexpr int PX = TX + 2;
@@ -64,6 +73,8 @@ struct StageArgs {
     DomainArgs d[2];         // 0 = lower, 1 = upper
     int32_t nx;
     int32_t nblocks;         // d[0].ntiles + d[1].ntiles
+    int32_t first;           // domain whose tiles take the first blocks
+    int32_t pad0;
     double dx, inv_dx;
     double gamma, gm1, gravity;
     double bu, bT;           // bulk coefficients of the interface flux

@@ -23,6 +23,20 @@ namespace mprk {
 
 namespace {
 
+#ifndef MPRK_FACE_PAIRS
+#define MPRK_FACE_PAIRS 0
+#endif
+// Keep face evaluations from being interleaved by the scheduler: the
+// interleaved form needs far more registers than the occupancy allows.
+#ifndef MPRK_FACE_SEQ
+#define MPRK_FACE_SEQ 0
+#endif
+#if MPRK_FACE_SEQ
+#define FACE_SCHED_BARRIER() __builtin_amdgcn_sched_barrier(0)
+#else
+#define FACE_SCHED_BARRIER() ((void)0)
+#endif
+
 constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
 constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
 constexpr int LDS_G = 2 * TX;              // u, T of the cell across the interface
@@ -30,11 +44,39 @@ constexpr int LDS_O = NV * TX;             // conserved state of that cell
 constexpr int LDS_EX = NV * TZ * (TX + 1) + NV * (TZ + 1) * TX;  // face fluxes
 constexpr int LDS_N = LDS_Q + LDS_P + LDS_G + LDS_O;
 static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
+constexpr int LOAD_RG = NT / HX;                        // row groups of the loader
+constexpr int LOAD_THREADS = LOAD_RG * HX;
+constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG; // rows per loader thread
 
 __device__ __forceinline__ int wrapx(int c, int nx)
 {
     int r = c % nx;
     return r < 0 ? r + nx : r;
+}
+
+// 1/sqrt(x) for positive normal x: hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2 (quadratic convergence; a few ulp).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+
+// sqrt(x) = x / sqrt(x) for positive normal x (no scaling for subnormals,
+// zero or infinity, which a physical state never produces; a non-physical
+// one yields NaN, which the device status check reports).
+__device__ __forceinline__ double sqrt_nr(double x) { return x * rsqrt_nr(x); }
+
+// 1/x for positive normal x: hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
 }
 
 // Cell primitives.  Contraction is off so that the value is identical
@@ -45,7 +87,7 @@ __device__ __forceinline__ void primitives(double rho, double mx, double mz, dou
                                            double& T)
 {
 #pragma clang fp contract(off)
-    double ir = 1.0 / rho;
+    const double ir = rcp_nr(rho);
     u = mx * ir;
     w = mz * ir;
     double p = gm1 * (en - 0.5 * (mx * u + mz * w));
@@ -89,112 +131,122 @@ enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
 //   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; gam = interface
 //                     below.
 // For a wall the viscous flux is zero; at the interface it is the bulk flux.
-template <int DOM>
-__device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& D, const Lds& L,
-                                          int dir, int c, int r, int kind, double F[NV])
+// N independent faces are evaluated in lockstep so that their dependency
+// chains interleave.
+template <int DOM, int dir, int N>
+__device__ __forceinline__ void face_fluxes(const StageArgs& A, const DomainArgs& D, const Lds& L,
+                                            const int (&c)[N], const int (&r)[N],
+                                            const int (&kind)[N], double (&F)[N][NV])
 {
     const double gamma = A.gamma, gm1 = A.gm1;
-    const int sn = dir ? HX : 1;             // normal stride in the state tile
-    const int vn = dir ? 2 : 1;              // normal momentum component
-    const int vt = dir ? 1 : 2;              // tangential momentum component
-    const int base = qidx(0, r, c);
-    const int plane = HZ * HX;
+    constexpr int sn = dir ? HX : 1;         // normal stride in the state tile
+    constexpr int vn = dir ? 2 : 1;          // normal momentum component
+    constexpr int vt = dir ? 1 : 2;          // tangential momentum component
+    constexpr int plane = HZ * HX;
+    constexpr int comp[NV] = {0, vn, vt, 3};
 
     // Reconstruction of conserved variables with central cell gradients:
     // qL = q_c + (q_{c+1} - q_{c-1})/4, qR = q_{c+1} - (q_{c+2} - q_c)/4.
-    double qL[NV], qR[NV];
-    {
-        const int comp[NV] = {0, vn, vt, 3};
+    double qL[N][NV], qR[N][NV];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int base = qidx(0, r[n], c[n]);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const double* s = L.q + comp[k] * plane + base;
-            double qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
-            qL[k] = q0 + 0.25 * (q1 - qm);
-            qR[k] = q1 - 0.25 * (q2 - q0);
+            const double qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
+            qL[n][k] = q0 + 0.25 * (q1 - qm);
+            qR[n][k] = q1 - 0.25 * (q2 - q0);
         }
-    }
-    if (kind == FACE_TOP) {
-        qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3];
-    } else if (kind == FACE_BOTTOM) {
-        qL[0] = qR[0]; qL[1] = -qR[1]; qL[2] = qR[2]; qL[3] = qR[3];
+        if (kind[n] == FACE_TOP) {
+            qR[n][0] = qL[n][0]; qR[n][1] = -qL[n][1]; qR[n][2] = qL[n][2]; qR[n][3] = qL[n][3];
+        } else if (kind[n] == FACE_BOTTOM) {
+            qL[n][0] = qR[n][0]; qL[n][1] = -qR[n][1]; qL[n][2] = qR[n][2]; qL[n][3] = qR[n][3];
+        }
     }
 
     // Local Lax-Friedrichs flux, lambda = max(|u_n| + a) over qL, qR and the
-    // Roe average (sqrt(rho)-weighted velocity and total enthalpy).
-    const double rL = 1.0 / qL[0], rR = 1.0 / qR[0];
-    const double unL = qL[1] * rL, utL = qL[2] * rL;
-    const double unR = qR[1] * rR, utR = qR[2] * rR;
-    const double pL = gm1 * (qL[3] - 0.5 * (qL[1] * unL + qL[2] * utL));
-    const double pR = gm1 * (qR[3] - 0.5 * (qR[1] * unR + qR[2] * utR));
-    const double aL = sqrt(gamma * pL * rL);
-    const double aR = sqrt(gamma * pR * rR);
-    const double sL = sqrt(qL[0]), sR = sqrt(qR[0]);
-    const double iw = 1.0 / (sL + sR);
-    const double unr = (sL * unL + sR * unR) * iw;
-    const double utr = (sL * utL + sR * utR) * iw;
-    const double HL = (qL[3] + pL) * rL, HR = (qR[3] + pR) * rR;
-    const double Hr = (sL * HL + sR * HR) * iw;
-    const double ar = sqrt(gm1 * (Hr - 0.5 * (unr * unr + utr * utr)));
-    const double lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
-    const double hl = 0.5 * lam;
-    F[0] = 0.5 * (qL[1] + qR[1]) - hl * (qR[0] - qL[0]);
-    F[1] = 0.5 * (qL[1] * unL + qR[1] * unR + pL + pR) - hl * (qR[1] - qL[1]);
-    F[2] = 0.5 * (qL[2] * unL + qR[2] * unR) - hl * (qR[2] - qL[2]);
-    F[3] = 0.5 * ((qL[3] + pL) * unL + (qR[3] + pR) * unR) - hl * (qR[3] - qL[3]);
+    // Roe average (sqrt(rho)-weighted velocity and total enthalpy).  One
+    // reciprocal square root per side gives 1/rho and sqrt(rho).
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const double* l = qL[n];
+        const double* q = qR[n];
+        const double yL = rsqrt_nr(l[0]), yR = rsqrt_nr(q[0]);
+        const double rL = yL * yL, rR = yR * yR;
+        const double sL = l[0] * yL, sR = q[0] * yR;
+        const double unL = l[1] * rL, utL = l[2] * rL;
+        const double unR = q[1] * rR, utR = q[2] * rR;
+        const double pL = gm1 * (l[3] - 0.5 * (l[1] * unL + l[2] * utL));
+        const double pR = gm1 * (q[3] - 0.5 * (q[1] * unR + q[2] * utR));
+        const double aL = sqrt_nr(gamma * pL * rL);
+        const double aR = sqrt_nr(gamma * pR * rR);
+        const double iw = rcp_nr(sL + sR);
+        const double unr = (sL * unL + sR * unR) * iw;
+        const double utr = (sL * utL + sR * utR) * iw;
+        const double HL = (l[3] + pL) * rL, HR = (q[3] + pR) * rR;
+        const double Hr = (sL * HL + sR * HR) * iw;
+        const double ar = sqrt_nr(gm1 * (Hr - 0.5 * (unr * unr + utr * utr)));
+        const double lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
+        const double hl = 0.5 * lam;
+        F[n][0] = 0.5 * (l[1] + q[1]) - hl * (q[0] - l[0]);
+        F[n][1] = 0.5 * (l[1] * unL + q[1] * unR + pL + pR) - hl * (q[1] - l[1]);
+        F[n][2] = 0.5 * (l[2] * unL + q[2] * unR) - hl * (q[2] - l[2]);
+        F[n][3] = 0.5 * ((l[3] + pL) * unL + (q[3] + pR) * unR) - hl * (q[3] - l[3]);
+    }
 
-    if (kind == FACE_INTERIOR) {
-        // Common values: averaged velocity, normal derivative by finite
-        // difference, tangential derivative by averaging cell gradients.
-        const int pb = pidx(0, r, c);
-        const int pn = dir ? PX : 1;
-        const int pt = dir ? 1 : PX;
-        const int fn = dir ? 1 : 0;          // normal velocity in the primitive tile
-        const int ft = dir ? 0 : 1;
-        const int pp = PZ * PX;
-        const double* Un = L.p + fn * pp + pb;
-        const double* Ut = L.p + ft * pp + pb;
-        const double* Tt = L.p + 2 * pp + pb;
-        const double inv_n = dir ? D.inv_dz : A.inv_dx;
-        const double inv_t4 = 0.25 * (dir ? A.inv_dx : D.inv_dz);
-        const double unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
-        const double dn_un = (unB - unA) * inv_n;
-        const double dn_ut = (utB - utA) * inv_n;
-        const double dn_T = (Tt[pn] - Tt[0]) * inv_n;
-        const double dt_un = (Un[pt] - Un[-pt] + Un[pn + pt] - Un[pn - pt]) * inv_t4;
-        const double dt_ut = (Ut[pt] - Ut[-pt] + Ut[pn + pt] - Ut[pn - pt]) * inv_t4;
-        const double mu = D.mu;
-        const double snn = mu * ((4.0 / 3.0) * dn_un - (2.0 / 3.0) * dt_ut);
-        const double snt = mu * (dn_ut + dt_un);
-        F[1] -= snn;
-        F[2] -= snt;
-        F[3] -= 0.5 * (unA + unB) * snn + 0.5 * (utA + utB) * snt + D.kappa * dn_T;
-    } else {
-        const bool gam = (kind == FACE_TOP) ? D.gamma_top : D.gamma_bot;
-        if (gam) {
-            // Only z-faces reach here: normal = w, tangential = u.
-            double u1, T1, u2, T2;
-            if (DOM == 0) {   // interface above the lower domain's top row r
-                u1 = L.p[pidx(0, r, c)];
-                T1 = L.p[pidx(2, r, c)];
-                u2 = L.g[c];
-                T2 = L.g[TX + c];
-            } else {          // interface below the upper domain's bottom row r+1
-                u1 = L.g[c];
-                T1 = L.g[TX + c];
-                u2 = L.p[pidx(0, r + 1, c)];
-                T2 = L.p[pidx(2, r + 1, c)];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        if (kind[n] == FACE_INTERIOR) {
+            // Common values: averaged velocity, normal derivative by finite
+            // difference, tangential derivative by averaging cell gradients.
+            const int pb = pidx(0, r[n], c[n]);
+            constexpr int pn = dir ? PX : 1;
+            constexpr int pt = dir ? 1 : PX;
+            constexpr int fn = dir ? 1 : 0;  // normal velocity in the primitive tile
+            constexpr int ft = dir ? 0 : 1;
+            constexpr int pp = PZ * PX;
+            const double* Un = L.p + fn * pp + pb;
+            const double* Ut = L.p + ft * pp + pb;
+            const double* Tt = L.p + 2 * pp + pb;
+            const double inv_n = dir ? D.inv_dz : A.inv_dx;
+            const double inv_t4 = 0.25 * (dir ? A.inv_dx : D.inv_dz);
+            const double unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
+            const double dn_un = (unB - unA) * inv_n;
+            const double dn_ut = (utB - utA) * inv_n;
+            const double dn_T = (Tt[pn] - Tt[0]) * inv_n;
+            const double dt_un = (Un[pt] - Un[-pt] + Un[pn + pt] - Un[pn - pt]) * inv_t4;
+            const double dt_ut = (Ut[pt] - Ut[-pt] + Ut[pn + pt] - Ut[pn - pt]) * inv_t4;
+            const double mu = D.mu;
+            const double snn = mu * ((4.0 / 3.0) * dn_un - (2.0 / 3.0) * dt_ut);
+            const double snt = mu * (dn_ut + dt_un);
+            F[n][1] -= snn;
+            F[n][2] -= snt;
+            F[n][3] -= 0.5 * (unA + unB) * snn + 0.5 * (utA + utB) * snt + D.kappa * dn_T;
+        } else {
+            const bool gam = (kind[n] == FACE_TOP) ? D.gamma_top : D.gamma_bot;
+            if (gam) {
+                // Only z-faces reach here: normal = w, tangential = u.
+                double u1, T1, u2, T2;
+                if (DOM == 0) {   // interface above the lower domain's top row r
+                    u1 = L.p[pidx(0, r[n], c[n])];
+                    T1 = L.p[pidx(2, r[n], c[n])];
+                    u2 = L.g[c[n]];
+                    T2 = L.g[TX + c[n]];
+                } else {          // interface below the upper domain's bottom row r+1
+                    u1 = L.g[c[n]];
+                    T1 = L.g[TX + c[n]];
+                    u2 = L.p[pidx(0, r[n] + 1, c[n])];
+                    T2 = L.p[pidx(2, r[n] + 1, c[n])];
+                }
+                double f1, f3;
+                interface_flux(A, u1, T1, u2, T2, f1, f3);
+                F[n][2] -= f1;   // tangential momentum (x) component
+                F[n][3] -= f3;
             }
-            double f1, f3;
-            interface_flux(A, u1, T1, u2, T2, f1, f3);
-            F[2] -= f1;   // tangential momentum (x) component
-            F[3] -= f3;
         }
     }
 }
-
-struct FaceJob {
-    int dir, c, r, kind, valid;
-};
 
 template <int DOM>
 __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
@@ -220,33 +272,59 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + nrows == nz)
                                       : (D.gamma_bot && z0 == 0);
 
-    // ---- stage the state tile (periodic in x, mirror rows beyond the domain)
-    for (int idx = tid; idx < LDS_Q; idx += NT) {
-        const int v = idx / (HZ * HX);
-        const int rem = idx - v * (HZ * HX);
-        const int zr = rem / HX;
-        const int xc = rem - zr * HX;
+    const int c = tid % TX;
+    const int r0 = 2 * (tid / TX);
+    const bool ok0 = (c < ncols) && (r0 < nrows);
+    const bool ok1 = (c < ncols) && (r0 + 1 < nrows);
+
+    // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
+    // Each of LOAD_THREADS threads owns one tile column and LOAD_ROWS rows
+    // (stride LOAD_RG); all its global loads are issued before any is used.
+    if (tid < LOAD_THREADS) {
+        const int xc = tid % HX, rg = tid / HX;
         const int col = wrapx(x0 + xc - 2, nx);
-        int row = z0 + zr - 2;
-        bool mir = false;
-        if (row < 0) { row = 0; mir = true; }
-        else if (row >= nz) { row = nz - 1; mir = true; }
-        double val;
-        if (D.use_ret && (row < D.b_lo || row >= D.b_hi)) {
-            int rr = row - D.ret_lo;
-            rr = rr < 0 ? 0 : (rr > 1 ? 1 : rr);
-            val = D.ret_in[(size_t)(v * 2 + rr) * nx + col];
-        } else {
-            val = D.qin[((size_t)v * nz + row) * nx + col];
+        double val[LOAD_ROWS][NV];
+        bool neg[LOAD_ROWS];
+#pragma unroll
+        for (int k = 0; k < LOAD_ROWS; ++k) {
+            const int zr = rg + LOAD_RG * k;
+            neg[k] = false;
+            if (zr < HZ) {
+                int row = z0 + zr - 2;
+                if (row < 0) { row = 0; neg[k] = true; }
+                else if (row >= nz) { row = nz - 1; neg[k] = true; }
+                const double* src;
+                size_t plane;
+                if (D.use_ret && (row < D.b_lo || row >= D.b_hi)) {
+                    int rr = row - D.ret_lo;
+                    rr = rr < 0 ? 0 : (rr > 1 ? 1 : rr);
+                    src = D.ret_in + (size_t)rr * nx + col;
+                    plane = 2 * (size_t)nx;
+                } else {
+                    src = D.qin + (size_t)row * nx + col;
+                    plane = (size_t)nz * nx;
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) val[k][v] = src[v * plane];
+            }
         }
-        if (mir && v == 2) val = -val;
-        L.q[idx] = val;
+#pragma unroll
+        for (int k = 0; k < LOAD_ROWS; ++k) {
+            const int zr = rg + LOAD_RG * k;
+            if (zr < HZ) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    L.q[(v * HZ + zr) * HX + xc] = (v == 2 && neg[k]) ? -val[k][v] : val[k][v];
+            }
+        }
     }
-    if (has_gamma && tid < NV * TX) {
-        const int v = tid / TX, c = tid - v * TX;
-        const int col = wrapx(x0 + c, nx);
+    if (has_gamma) {
         const int orow = (DOM == 0) ? 0 : O.nz - 1;
-        L.o[tid] = O.qin[((size_t)v * O.nz + orow) * nx + col];
+        for (int i = tid; i < NV * TX; i += NT) {
+            const int v = i / TX, c = i - v * TX;
+            const int col = wrapx(x0 + c, nx);
+            L.o[i] = O.qin[((size_t)v * O.nz + orow) * nx + col];
+        }
     }
     __syncthreads();
 
@@ -270,12 +348,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     }
     __syncthreads();
 
-    // ---- faces: slots 0,1 = x-faces right of the two cells, 2,3 = z-faces
-    // above them, 4 = tile-edge faces (left column, bottom row) in wave 0.
-    const int c = tid % TX;
-    const int r0 = 2 * (tid / TX);
-    const bool ok0 = (c < ncols) && (r0 < nrows);
-    const bool ok1 = (c < ncols) && (r0 + 1 < nrows);
+    // ---- faces
 
     double qc[2][NV];
 #pragma unroll
@@ -284,52 +357,101 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
         qc[1][v] = L.q[qidx(v, r0 + 1, c)];
     }
 
-    FaceJob job[5];
-    job[0] = {0, c, r0, FACE_INTERIOR, ok0};
-    job[1] = {0, c, r0 + 1, FACE_INTERIOR, ok1};
-    job[2] = {1, c, r0, (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR, ok0};
-    job[3] = {1, c, r0 + 1, (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR, ok1};
-    if (tid < TZ) {
-        job[4] = {0, -1, tid, FACE_INTERIOR, tid < nrows};
-    } else if (tid < TZ + TX) {
-        const int cc = tid - TZ;
-        job[4] = {1, cc, -1, (z0 == 0) ? FACE_BOTTOM : FACE_INTERIOR, cc < ncols};
-    } else {
-        job[4] = {0, 0, 0, FACE_INTERIOR, 0};
-    }
+    // Slots 0,1: x-faces right of the two cells; 2,3: z-faces above them;
+    // 4: the tile's left column of x-faces (wave 0) and bottom row of
+    // z-faces (wave 1), so that no wave runs both directions.
+    const int kind2 = (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
+    const int kind3 = (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
+    const bool ex_x4 = tid < TZ && tid < nrows;
+    const int ez = tid - 64;
+    const bool ex_z4 = ez >= 0 && ez < TX && ez < ncols;
+    const int kind4 = (z0 == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
     double F[5][NV];
+    {
+        const int cx[2] = {c, c}, rx[2] = {r0, r0 + 1};
+        const int kx[2] = {FACE_INTERIOR, FACE_INTERIOR}, kz[2] = {kind2, kind3};
+#if MPRK_FACE_PAIRS
+        double Fp[2][NV];
+        if (ok0 || ok1) {
+            face_fluxes<DOM, 0, 2>(A, D, L, cx, rx, kx, Fp);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        if (job[j].valid) face_flux<DOM>(A, D, L, job[j].dir, job[j].c, job[j].r, job[j].kind, F[j]);
+            for (int v = 0; v < NV; ++v) { F[0][v] = Fp[0][v]; F[1][v] = Fp[1][v]; }
+            face_fluxes<DOM, 1, 2>(A, D, L, cx, rx, kz, Fp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { F[2][v] = Fp[0][v]; F[3][v] = Fp[1][v]; }
+        }
+#else
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!(h ? ok1 : ok0)) continue;
+            const int c1[1] = {c}, r1[1] = {rx[h]}, k1[1] = {FACE_INTERIOR}, k2[1] = {kz[h]};
+            double Fs[1][NV];
+            face_fluxes<DOM, 0, 1>(A, D, L, c1, r1, k1, Fs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[h][v] = Fs[0][v];
+            FACE_SCHED_BARRIER();
+            face_fluxes<DOM, 1, 1>(A, D, L, c1, r1, k2, Fs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[2 + h][v] = Fs[0][v];
+            FACE_SCHED_BARRIER();
+        }
+#endif
+        double Fs[1][NV];
+        if (ex_x4) {
+            const int c1[1] = {-1}, r1[1] = {tid}, k1[1] = {FACE_INTERIOR};
+            face_fluxes<DOM, 0, 1>(A, D, L, c1, r1, k1, Fs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
+        }
+        if (ex_z4) {
+            const int c1[1] = {ez}, r1[1] = {-1}, k1[1] = {kind4};
+            face_fluxes<DOM, 1, 1>(A, D, L, c1, r1, k1, Fs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
+        }
+    }
+
+    // Pointwise global reads of the substep base U for the combination; they
+    // complete while the fluxes are exchanged.
+    const int col = x0 + c;
+    const size_t plane = (size_t)nz * nx;
+    const size_t nbx = (size_t)(D.b_hi - D.b_lo) * nx;
+    double Ub[2][NV];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int row = z0 + r0 + h;
+        const bool ok = h ? ok1 : ok0;
+        const bool inb = (row >= D.b_lo && row < D.b_hi);
+        const Combine& cb = inb ? D.buf : D.main;
+        const size_t id = (size_t)row * nx + col;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ub[h][v] = 0.0;
+        if (ok && cb.mode != MODE_RHS && cb.alpha != 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ub[h][v] = D.base[v * plane + id];
+        }
     }
     __syncthreads();   // all LDS reads of the staged state are done
 
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        if (!job[j].valid) continue;
-        const int dir = job[j].dir;
-        // Back from the face-normal frame to (rho, rho u, rho w, rho E).
-        const double g1 = dir ? F[j][2] : F[j][1];
-        const double g2 = dir ? F[j][1] : F[j][2];
-        double* e;
-        int stride;
-        if (dir == 0) {
-            e = ex_x + job[j].r * (TX + 1) + job[j].c + 1;
-            stride = TZ * (TX + 1);
-        } else {
-            e = ex_z + (job[j].r + 1) * TX + job[j].c;
-            stride = (TZ + 1) * TX;
-        }
-        e[0] = F[j][0];
-        e[stride] = g1;
-        e[2 * stride] = g2;
-        e[3 * stride] = F[j][3];
-    }
+    // Fluxes back from the face-normal frame to (rho, rho u, rho w, rho E).
+    auto put_x = [&](int cc, int rr, const double* f) {
+        double* e = ex_x + rr * (TX + 1) + cc + 1;
+        constexpr int st = TZ * (TX + 1);
+        e[0] = f[0]; e[st] = f[1]; e[2 * st] = f[2]; e[3 * st] = f[3];
+    };
+    auto put_z = [&](int cc, int rr, const double* f) {
+        double* e = ex_z + (rr + 1) * TX + cc;
+        constexpr int st = (TZ + 1) * TX;
+        e[0] = f[0]; e[st] = f[2]; e[2 * st] = f[1]; e[3 * st] = f[3];
+    };
+    if (ok0) { put_x(c, r0, F[0]); put_z(c, r0, F[2]); }
+    if (ok1) { put_x(c, r0 + 1, F[1]); put_z(c, r0 + 1, F[3]); }
+    if (ex_x4) put_x(-1, tid, F[4]);
+    if (ex_z4) put_z(ez, -1, F[4]);
     __syncthreads();
 
     // ---- divergence, source and stage combination
-    const int col = x0 + c;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const bool ok = h ? ok1 : ok0;
@@ -347,8 +469,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
         R[3] += qc[h][2] * A.gravity;
 
         const bool inb = (row >= D.b_lo && row < D.b_hi);
-        const Combine cb = inb ? D.buf : D.main;
-        const size_t plane = (size_t)nz * nx;
+        const Combine& cb = inb ? D.buf : D.main;
         const size_t id = (size_t)row * nx + col;
         if (cb.mode == MODE_RHS) {
 #pragma unroll
@@ -360,30 +481,26 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
         } else {
             // Increment form of alpha U + beta (Qin + h R): U + beta (Qin - U)
             // + beta h R, exact when R = 0 and Qin = U.
-            double U[NV], inc[NV];
+            double inc[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                U[v] = D.base[v * plane + id];
-                inc[v] = cb.beta * (qc[h][v] - U[v]) + cb.bh * R[v];
-            }
+            for (int v = 0; v < NV; ++v) inc[v] = cb.beta * (qc[h][v] - Ub[h][v]) + cb.bh * R[v];
             if (cb.mode == MODE_STAGE) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) D.out[v * plane + id] = U[v] + inc[v];
+                for (int v = 0; v < NV; ++v) D.out[v * plane + id] = Ub[h][v] + inc[v];
             } else {
                 // Buffer: accumulate the increments of the m trial steps and
                 // add their mean to q^B_n after the last one.
-                const size_t nb = (size_t)(D.b_hi - D.b_lo);
                 const size_t ia = (size_t)(row - D.b_lo) * nx + col;
                 if (cb.mode == MODE_ACC_FIRST) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) D.acc[v * nb * nx + ia] = inc[v];
+                    for (int v = 0; v < NV; ++v) D.acc[v * nbx + ia] = inc[v];
                 } else if (cb.mode == MODE_ACC_ADD) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) D.acc[v * nb * nx + ia] += inc[v];
+                    for (int v = 0; v < NV; ++v) D.acc[v * nbx + ia] += inc[v];
                 } else {
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        D.out[v * plane + id] = U[v] + (D.acc[v * nb * nx + ia] + inc[v]) * A.inv_m;
+                        D.out[v * plane + id] = Ub[h][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m;
                 }
             }
         }
@@ -395,12 +512,35 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     }
 }
 
-__global__ __launch_bounds__(NT) void stage_kernel(const StageArgs A)
+// Workgroups are dispatched to the 8 XCDs round-robin (block j to XCD j % 8).
+// Give each XCD a contiguous range of the n tiles so that neighbouring tiles,
+// which share halo rows and columns, meet in the same L2.
+__device__ __forceinline__ int xcd_contiguous(int j, int n)
+{
+    constexpr int NXCD = 8;
+    const int x = j % NXCD, i = j / NXCD;
+    const int per = n / NXCD, rem = n % NXCD;
+    return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+#ifndef MPRK_WAVES_PER_EU
+#define MPRK_WAVES_PER_EU 3
+#endif
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
+void stage_kernel(const StageArgs A)
 {
     __shared__ double lds[LDS_N];
+    // Domain A.first takes the first blocks (the host puts the domain with
+    // the shorter tiles first so they do not form a tail).
     const int b = blockIdx.x;
-    if (b < A.d[0].ntiles) stage_tile<0>(A, b, lds);
-    else stage_tile<1>(A, b - A.d[0].ntiles, lds);
+    const int n0 = A.d[A.first].ntiles;
+    const int dom = (b < n0) ? A.first : 1 - A.first;
+    int t = (b < n0) ? b : b - n0;
+    // The second domain's blocks keep j % 8 == XCD only if n0 % 8 == 0.
+    if (b < n0 || (n0 % 8) == 0) t = xcd_contiguous(t, (b < n0) ? n0 : A.nblocks - n0);
+    if (dom == 0) stage_tile<0>(A, t, lds);
+    else stage_tile<1>(A, t, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,7 +15,9 @@ OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3,
 REGION_F, REGION_B, REGION_S, REGION_ALL = 1, 2, 4, 7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmprk.so")
+# MPRK_LIB selects another build of the same library (side-by-side variants);
+# by default the in-tree build next to this file is used.
+LIB_PATH = os.environ.get("MPRK_LIB") or os.path.join(_HERE, "libmprk.so")
 
 
 class mprk_config(ctypes.Structure):
