@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--exec", choices=["persistent", "launch"], default="persistent",
+                    help="persistent: one cooperative launch per check segment; launch: one per stage")
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
@@ -116,7 +118,8 @@ def main():
     tu0 = torch.from_numpy(qu0).to(dev)
     tl, tu = tl0.clone(), tu0.clone()
     cfg = mprk.config_of_workload(w)
-    sol = mprk.Solver(cfg, tl, tu)
+    exec_mode = mprk.EXEC_PERSISTENT if args.exec == "persistent" else mprk.EXEC_LAUNCH
+    sol = mprk.Solver(cfg, tl, tu, exec_mode=exec_mode)
     dt = sol.stable_dt(w.cfl, w.dnum)
 
     # ---- warm-up, then restore the initial state
@@ -155,21 +158,33 @@ def main():
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
 
-    # ---- stage-kernel time per launch.  Stage launches run back to back on
-    # the stream, so the event time of the timed region divided by the number
-    # of stage launches is the average launch duration (the reductions every
-    # check_every steps are included, about 1%).  Events bracketing every
-    # launch are also reported; they add a little overhead per launch.
-    sol.profile(True)
-    for _ in range(args.profile_steps):
-        sol.step(dt)
-    k_ms, k_n = sol.profile_take()
-    sol.profile(False)
+    # ---- dominant kernel time per launch.  Launches run back to back on the
+    # stream, so the event time of the timed region divided by the number of
+    # launches of the dominant kernel is its average duration (the reductions
+    # every check_every steps are included, about 1%).  In launch mode that
+    # kernel is the stage kernel (m*s launches per step; events bracketing
+    # every launch are also reported); in persistent mode it is the
+    # persistent kernel (one launch per check segment of check_every steps).
     launches_per_step = m * s
-    avg_launch_s = gpu_ms * 1e-3 / (K * launches_per_step)
-    bytes_per_launch = bytes_step / launches_per_step
+    if args.exec == "launch":
+        sol.profile(True)
+        for _ in range(args.profile_steps):
+            sol.step(dt)
+        k_ms, k_n = sol.profile_take()
+        sol.profile(False)
+        kernel_name = "stage_kernel"
+        n_launch = K * launches_per_step
+        bytes_per_launch = bytes_step / launches_per_step
+        bracketed = round(k_ms * 1e3 / k_n, 3)
+    else:
+        kernel_name = "persistent_kernel"
+        seg = args.check_every if args.check_every > 0 else K
+        n_launch = -(-K // seg)
+        bytes_per_launch = bytes_step * K / n_launch
+        bracketed = None
+    avg_launch_s = gpu_ms * 1e-3 / n_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = traffic_from_profiles(args.workload)
+    traffic = traffic_from_profiles(args.workload) if args.exec == "launch" else None
     if traffic is not None:
         traffic = round(traffic / avg_launch_s / 1e9, 1)   # measured HBM GB/s
     roofline = {
@@ -179,15 +194,14 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "traffic_bytes_per_launch": traffic_from_profiles(args.workload),
-        "kernel": "stage_kernel",
+        "kernel": kernel_name,
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
-        "avg_launch_us_bracketed": round(k_ms * 1e3 / k_n, 3),
+        "avg_launch_us_bracketed": bracketed,
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
-        "kernel_time_per_step_us": round(avg_launch_s * launches_per_step * 1e6, 2),
+        "stage_time_us": round(gpu_ms * 1e3 / (K * launches_per_step), 3),
     }
-    print("# stage kernel: %.2f us/launch, %.0f GB/s algorithmic" %
-          (avg_launch_s * 1e6, achieved), file=sys.stderr, flush=True)
+    print("# %s: %.2f us/launch, %.0f GB/s algorithmic" %
+          (kernel_name, avg_launch_s * 1e6, achieved), file=sys.stderr, flush=True)
 
     out = {
         "metric": "cell-stage updates/s, MPRK vs single-rate RK at equal error; p50/p99 latency",
@@ -208,6 +222,7 @@ def main():
             "base": "SSP-RK3" if s == 3 else "RK2", "m": m, "n_buffer": w.n_buffer,
             "dt": dt, "cfl": w.cfl, "diffusion_number": w.dnum,
             "check_every": args.check_every,
+            "exec": args.exec,
             "cell_stages_per_step": cs_step,
             "parallelism": "single GPU",
         },
@@ -224,7 +239,7 @@ def main():
     if not args.no_sr:
         tl.copy_(tl0)
         tu.copy_(tu0)
-        sr = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu)
+        sr = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu, exec_mode=exec_mode)
         sr.run(dt / m, 2, check_every=0)
         tl.copy_(tl0)
         tu.copy_(tu0)
@@ -248,7 +263,7 @@ def main():
             nref = 8
             tl.copy_(tl0)
             tu.copy_(tu0)
-            ref = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu)
+            ref = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu, exec_mode=exec_mode)
             ref.run(dt / (m * nref), K * m * nref, check_every=K * m)
             torch.cuda.synchronize()
             rf = (tl.cpu().numpy(), tu.cpu().numpy())

@@ -60,7 +60,18 @@ enum mprk_status {
     MPRK_EWORKSPACE = -3,   /* workspace missing, too small or not 256-B aligned     */
     MPRK_EHIP = -4,         /* a HIP runtime call or kernel launch failed            */
     MPRK_ENONFINITE = -5,   /* non-finite value, rho <= 0 or p <= 0 detected         */
-    MPRK_EUNSUPPORTED = -6  /* valid request this build does not implement           */
+    MPRK_EUNSUPPORTED = -6, /* valid request this build or device does not support   */
+    MPRK_ETIMEOUT = -7      /* persistent execution: a tile waited over its time limit
+                               for a neighbour (the run was aborted; the state is not
+                               a completed step)                                      */
+};
+
+/* How mprk_step / mprk_run execute a slow step. */
+enum mprk_exec {
+    MPRK_EXEC_LAUNCH = 0,     /* one kernel launch per stage (m*s per slow step)        */
+    MPRK_EXEC_PERSISTENT = 1  /* one cooperative launch per run segment: workgroups stay
+                                 resident and start a tile's next stage as soon as the
+                                 tiles it reads have finished the previous one           */
 };
 
 /* Regions of eq. (semi-discretized-coupled-model), as bits. */
@@ -165,6 +176,18 @@ int mprk_diagnostics(mprk_ctx* ctx, mprk_stats* out);
  * or wave speeds. */
 int mprk_stable_dt(const mprk_config* cfg, const mprk_stats* st, double cr, double dn,
                    double* dt_out);
+
+/* Select the execution of later mprk_step / mprk_run calls (default
+ * MPRK_EXEC_LAUNCH).  Both give bit-identical results: every cell is
+ * computed by the same code from the same inputs.  The persistent mode needs
+ * cooperative launch support (else mprk_run returns MPRK_EUNSUPPORTED); its
+ * waits are bounded (2 s), so a run can end with MPRK_ETIMEOUT but never
+ * hangs.  Kernel timing (mprk_profile_*) covers the launch mode only. */
+int mprk_set_exec(mprk_ctx* ctx, int mode);
+
+/* Longest time (seconds, default 2) a tile of a persistent run waits for a
+ * neighbour before the run is aborted with MPRK_ETIMEOUT. */
+int mprk_set_wait_limit(mprk_ctx* ctx, double seconds);
 
 /* Kernel timing aid.  While enabled, every stage launch is bracketed by a
  * pair of HIP events recorded on the context's stream (host-side event

@@ -52,6 +52,11 @@ struct Layout {
     size_t off_ret[3];        // retained slow rows per base stage
     size_t off_acc;
     size_t off_partial, off_final;
+    size_t off_ptab;          // persistent execution: stage table
+    size_t off_ptiles;        //   tile table
+    size_t off_pmember;       //   member record
+    size_t off_pdone;         //   progress counters, then the abort flag
+    int ntiles;               // fixed tiles of both domains
     size_t total;
 };
 
@@ -82,6 +87,16 @@ bool layout_of(const mprk_config* c, Layout* L)
     off += round_up((size_t)2 * RED_BLOCKS * RED_FIELDS * sizeof(double));
     L->off_final = off;
     off += round_up((size_t)2 * RED_FIELDS * sizeof(double));
+    const int tiles_x = (c->nx + TX - 1) / TX;
+    L->ntiles = tiles_x * ((c->nz_lower + TZ - 1) / TZ + (c->nz_upper + TZ - 1) / TZ);
+    L->off_ptab = off;
+    off += round_up((size_t)c->m * s * sizeof(StageArgs));
+    L->off_ptiles = off;
+    off += round_up((size_t)L->ntiles * sizeof(TileRef));
+    L->off_pmember = off;
+    off += round_up(sizeof(MemberRun));
+    L->off_pdone = off;
+    off += round_up((size_t)(L->ntiles + 1) * sizeof(int32_t));
     L->total = off;
     return true;
 }
@@ -99,6 +114,16 @@ struct mprk_ctx {
     int b_lo, b_hi, ret_lo; // buffer rows and retained rows of the slow domain
     int64_t steps;
     double host_final[2 * RED_FIELDS];
+    int exec = MPRK_EXEC_LAUNCH;
+    double ptab_dt = 0.0;                     // dt of the uploaded stage table (0: none)
+    bool ptiles_ready = false;
+    int pgrid = 0;                            // persistent grid size
+    int64_t wait_ticks = 0;
+    double wait_seconds = 2.0;
+    // Host copies of the persistent tables (the asynchronous uploads read them).
+    std::vector<StageArgs> h_tab;
+    std::vector<TileRef> h_tiles;
+    MemberRun h_mr;
     bool prof_on = false;
     size_t prof_used = 0;                     // event pairs recorded since the last take
     std::vector<hipEvent_t> prof_ev;          // start/stop pairs, reused
@@ -122,7 +147,8 @@ const char* mprk_strerror(int code)
     case MPRK_EWORKSPACE: return "workspace missing, too small or misaligned";
     case MPRK_EHIP: return "HIP runtime error";
     case MPRK_ENONFINITE: return "non-finite or non-physical state";
-    case MPRK_EUNSUPPORTED: return "not supported by this build";
+    case MPRK_EUNSUPPORTED: return "not supported by this build or device";
+    case MPRK_ETIMEOUT: return "a persistent-kernel wait timed out (run aborted)";
     default: return "unknown status";
     }
 }
@@ -319,7 +345,7 @@ void set_rows(DomainArgs& D, int nx, int lo, int hi)
     D.row_lo = lo;
     D.row_hi = hi;
     D.tiles_x = (nx + TX - 1) / TX;
-    D.tiles_z = hi > lo ? (hi - lo + TZ - 1) / TZ : 0;
+    D.tiles_z = hi > lo ? (hi - 1) / TZ - lo / TZ + 1 : 0;   // fixed tiles meeting [lo, hi)
     D.ntiles = D.tiles_x * D.tiles_z;
 }
 
@@ -393,9 +419,14 @@ int mprk_rhs(mprk_ctx* c, const double* q_lower, const double* q_upper, double* 
     return launch(c, a);
 }
 
-int mprk_step(mprk_ctx* c, double dt)
+}  // extern "C"
+
+namespace {
+
+// Launch parameters of global stage (k, j) of a slow step of size dt
+// (Algorithm 1 in the low-storage substep form).
+StageArgs stage_args(mprk_ctx* c, double dt, int k, int j)
 {
-    if (!c || !(dt > 0) || !std::isfinite(dt)) return MPRK_EINVAL;
     const mprk_config& g = c->cfg;
     const int s = c->lay.s, m = g.m;
     const int F = c->fast, S = c->slow;
@@ -404,60 +435,184 @@ int mprk_step(mprk_ctx* c, double dt)
     const int nzF = F == 0 ? g.nz_lower : g.nz_upper;
     const int nzS = S == 0 ? g.nz_lower : g.nz_upper;
     const double hF = dt / m;
+    StageArgs a = base_args(c);
+    const double al = c->alpha[j - 1];
+    const bool last = (j == s);
+
+    // Fast domain: m substeps of dt/m of the base method.
+    DomainArgs& DF = a.d[F];
+    DF.qin = (j == 1) ? qF : c->stage(F, j - 1);
+    DF.base = qF;
+    DF.out = last ? qF : c->stage(F, j);
+    DF.main = combine(al, hF, MODE_STAGE);
+    DF.buf = DF.main;
+    set_rows(DF, g.nx, 0, nzF);
+
+    // Slow domain.
+    DomainArgs& DS = a.d[S];
+    DS.qin = (j == 1) ? qS : c->stage(S, j - 1);
+    DS.base = qS;
+    DS.out = last ? qS : c->stage(S, j);
+    if (m == 1) {
+        // Single rate: buffer and slow rows are the same base step.
+        DS.main = combine(al, dt, MODE_STAGE);
+        DS.buf = DS.main;
+        set_rows(DS, g.nx, 0, nzS);
+    } else {
+        DS.b_lo = c->b_lo;
+        DS.b_hi = c->b_hi;
+        DS.ret_lo = c->ret_lo;
+        DS.acc = c->acc();
+        // Buffer: each substep restarts from q^B_n with the full step; the
+        // results of the m trial steps are averaged.
+        int bmode = MODE_STAGE;
+        if (last) bmode = (k == 1) ? MODE_ACC_FIRST : (k < m ? MODE_ACC_ADD : MODE_ACC_FINAL);
+        DS.buf = combine(al, dt, bmode);
+        DS.main = combine(al, dt, MODE_STAGE);
+        if (k == 1) {
+            // Slow rows: one base step; keep the two rows next to the buffer of
+            // each stage value for the later substeps.
+            DS.ret_out = c->ret(j - 1);
+            set_rows(DS, g.nx, 0, nzS);
+        } else {
+            DS.use_ret = 1;
+            DS.ret_in = c->ret(j - 1);
+            set_rows(DS, g.nx, c->b_lo, c->b_hi);
+        }
+    }
+    return a;
+}
+
+int step_launches(mprk_ctx* c, double dt)
+{
+    const int s = c->lay.s, m = c->cfg.m;
     for (int k = 1; k <= m; ++k) {
         for (int j = 1; j <= s; ++j) {
-            StageArgs a = base_args(c);
-            const double al = c->alpha[j - 1];
-            const bool last = (j == s);
-
-            // Fast domain: m substeps of dt/m of the base method.
-            DomainArgs& DF = a.d[F];
-            DF.qin = (j == 1) ? qF : c->stage(F, j - 1);
-            DF.base = qF;
-            DF.out = last ? qF : c->stage(F, j);
-            DF.main = combine(al, hF, MODE_STAGE);
-            DF.buf = DF.main;
-            set_rows(DF, g.nx, 0, nzF);
-
-            // Slow domain.
-            DomainArgs& DS = a.d[S];
-            DS.qin = (j == 1) ? qS : c->stage(S, j - 1);
-            DS.base = qS;
-            DS.out = last ? qS : c->stage(S, j);
-            if (m == 1) {
-                // Single rate: buffer and slow rows are the same base step.
-                DS.main = combine(al, dt, MODE_STAGE);
-                DS.buf = DS.main;
-                set_rows(DS, g.nx, 0, nzS);
-            } else {
-                DS.b_lo = c->b_lo;
-                DS.b_hi = c->b_hi;
-                DS.ret_lo = c->ret_lo;
-                DS.acc = c->acc();
-                // Buffer: each substep restarts from q^B_n with the full step;
-                // the results of the m trial steps are averaged.
-                int bmode = MODE_STAGE;
-                if (last) bmode = (k == 1) ? MODE_ACC_FIRST : (k < m ? MODE_ACC_ADD : MODE_ACC_FINAL);
-                DS.buf = combine(al, dt, bmode);
-                if (k == 1) {
-                    // Slow rows: one base step; keep the two rows next to the
-                    // buffer of each stage value for the later substeps.
-                    DS.main = combine(al, dt, MODE_STAGE);
-                    DS.ret_out = c->ret(j - 1);
-                    set_rows(DS, g.nx, 0, nzS);
-                } else {
-                    DS.main = combine(al, dt, MODE_STAGE);  // not evaluated
-                    DS.use_ret = 1;
-                    DS.ret_in = c->ret(j - 1);
-                    set_rows(DS, g.nx, c->b_lo, c->b_hi);
-                }
-            }
+            StageArgs a = stage_args(c, dt, k, j);
             int rc = launch(c, a);
             if (rc != MPRK_OK) return rc;
         }
     }
-    c->steps += 1;
     return MPRK_OK;
+}
+
+// One persistent launch running nsteps slow steps.
+int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
+{
+    const mprk_config& g = c->cfg;
+    const int s = c->lay.s, m = g.m, ms = m * s;
+    char* ws = c->ws;
+    if (c->pgrid <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return MPRK_EHIP;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MPRK_EHIP;
+        int coop = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+            return MPRK_EUNSUPPORTED;
+        const int per_cu = persistent_blocks_per_cu();
+        if (per_cu <= 0) return MPRK_EHIP;
+        int grid = per_cu * prop.multiProcessorCount;
+        if (grid > c->lay.ntiles) grid = c->lay.ntiles;
+        c->pgrid = grid;
+        int rate_khz = 0;
+        if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+            rate_khz <= 0)
+            rate_khz = 100000;
+        c->wait_ticks = (int64_t)((double)rate_khz * 1000.0 * c->wait_seconds);
+    }
+    if (!c->ptiles_ready) {
+        const int tiles_x = (g.nx + TX - 1) / TX;
+        const int tz[2] = {(g.nz_lower + TZ - 1) / TZ, (g.nz_upper + TZ - 1) / TZ};
+        std::vector<TileRef>& tiles = c->h_tiles;
+        tiles.clear();
+        tiles.reserve(c->lay.ntiles);
+        for (int d = 0; d < 2; ++d)
+            for (int z = 0; z < tz[d]; ++z)
+                for (int x = 0; x < tiles_x; ++x) tiles.push_back(TileRef{0, d, x, z});
+        if (hipMemcpyAsync(ws + c->lay.off_ptiles, tiles.data(), tiles.size() * sizeof(TileRef),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return MPRK_EHIP;
+        c->ptiles_ready = true;
+    }
+    if (c->ptab_dt != dt) {
+        std::vector<StageArgs>& tab = c->h_tab;
+        tab.clear();
+        tab.reserve(ms);
+        for (int k = 1; k <= m; ++k)
+            for (int j = 1; j <= s; ++j) tab.push_back(stage_args(c, dt, k, j));
+        if (hipMemcpyAsync(ws + c->lay.off_ptab, tab.data(), tab.size() * sizeof(StageArgs),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return MPRK_EHIP;
+        c->ptab_dt = dt;
+    }
+    if ((int64_t)nsteps * ms > (int64_t)(1 << 30)) return MPRK_EINVAL;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    MemberRun& mr = c->h_mr;
+    std::memset(&mr, 0, sizeof mr);
+    mr.stages = (const StageArgs*)(ws + c->lay.off_ptab);
+    mr.nstages = (int32_t)(nsteps * ms);
+    mr.ms = ms;
+    mr.tiles_x = tiles_x;
+    mr.tiles_z[0] = (g.nz_lower + TZ - 1) / TZ;
+    mr.tiles_z[1] = (g.nz_upper + TZ - 1) / TZ;
+    mr.done_base[0] = 0;
+    mr.done_base[1] = tiles_x * mr.tiles_z[0];
+    if (hipMemcpyAsync(ws + c->lay.off_pmember, &mr, sizeof mr, hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+        return MPRK_EHIP;
+    int32_t* done = (int32_t*)(ws + c->lay.off_pdone);
+    if (launch_fill_i32(done, 0, c->lay.ntiles + 1, c->stream) != hipSuccess) return MPRK_EHIP;
+    PersistArgs P;
+    std::memset(&P, 0, sizeof P);
+    P.tiles = (const TileRef*)(ws + c->lay.off_ptiles);
+    P.members = (const MemberRun*)(ws + c->lay.off_pmember);
+    P.done = done;
+    P.abort_flag = done + c->lay.ntiles;
+    P.ntiles = c->lay.ntiles;
+    P.gmax = mr.nstages;
+    P.wait_ticks = c->wait_ticks;
+    if (launch_persistent(P, c->pgrid, c->stream) != hipSuccess) return MPRK_EHIP;
+    return MPRK_OK;
+}
+
+int advance(mprk_ctx* c, double dt, int64_t nsteps)
+{
+    if (nsteps <= 0) return MPRK_OK;
+    int rc;
+    if (c->exec == MPRK_EXEC_PERSISTENT) {
+        rc = run_persistent(c, dt, nsteps);
+    } else {
+        rc = MPRK_OK;
+        for (int64_t n = 0; n < nsteps && rc == MPRK_OK; ++n) rc = step_launches(c, dt);
+    }
+    if (rc == MPRK_OK) c->steps += nsteps;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mprk_set_exec(mprk_ctx* c, int mode)
+{
+    if (!c || (mode != MPRK_EXEC_LAUNCH && mode != MPRK_EXEC_PERSISTENT)) return MPRK_EINVAL;
+    c->exec = mode;
+    return MPRK_OK;
+}
+
+int mprk_set_wait_limit(mprk_ctx* c, double seconds)
+{
+    if (!c || !(seconds >= 0.0) || !(seconds <= 3600.0)) return MPRK_EINVAL;
+    c->wait_seconds = seconds;
+    c->pgrid = 0;   // recompute the tick limit at the next persistent launch
+    return MPRK_OK;
+}
+
+int mprk_step(mprk_ctx* c, double dt)
+{
+    if (!c || !(dt > 0) || !std::isfinite(dt)) return MPRK_EINVAL;
+    return advance(c, dt, 1);
 }
 
 static int run_reduce(mprk_ctx* c, mprk_stats* out)
@@ -484,7 +639,13 @@ static int run_reduce(mprk_ctx* c, mprk_stats* out)
     if (hipMemcpyAsync(c->host_final, r.final_, sizeof c->host_final, hipMemcpyDeviceToHost,
                        c->stream) != hipSuccess)
         return MPRK_EHIP;
+    int32_t aborted = 0;
+    if (c->exec == MPRK_EXEC_PERSISTENT &&
+        hipMemcpyAsync(&aborted, (int32_t*)(c->ws + c->lay.off_pdone) + c->lay.ntiles,
+                       sizeof aborted, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return MPRK_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MPRK_EHIP;
+    if (aborted) return MPRK_ETIMEOUT;
     mprk_stats st;
     std::memset(&st, 0, sizeof st);
     const double area[2] = {g.dx * g.dz_lower, g.dx * g.dz_upper};
@@ -541,14 +702,16 @@ int mprk_diagnostics(mprk_ctx* c, mprk_stats* out)
 int mprk_run(mprk_ctx* c, double dt, int64_t nsteps, int64_t check_every, mprk_stats* out)
 {
     if (!c || nsteps < 0) return MPRK_EINVAL;
+    if (nsteps > 0 && (!(dt > 0) || !std::isfinite(dt))) return MPRK_EINVAL;
     if (nsteps == 0) return run_reduce(c, out);
-    for (int64_t n = 1; n <= nsteps; ++n) {
-        int rc = mprk_step(c, dt);
+    const int64_t chunk = check_every > 0 ? check_every : nsteps;
+    for (int64_t done = 0; done < nsteps;) {
+        const int64_t n = std::min(chunk, nsteps - done);
+        int rc = advance(c, dt, n);
         if (rc != MPRK_OK) return rc;
-        if (n == nsteps || (check_every > 0 && n % check_every == 0)) {
-            rc = run_reduce(c, out);
-            if (rc != MPRK_OK) return rc;
-        }
+        done += n;
+        rc = run_reduce(c, out);
+        if (rc != MPRK_OK) return rc;
     }
     return MPRK_OK;
 }

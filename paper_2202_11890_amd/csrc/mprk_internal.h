@@ -56,7 +56,8 @@ struct DomainArgs {
                            // [b_lo, b_hi) when use_ret is set
     double* ret_out;       // if set: save Qin rows [ret_lo, ret_lo+2) here
     int32_t nz;
-    int32_t row_lo, row_hi;  // rows computed by this launch
+    int32_t row_lo, row_hi;  // rows computed by this launch (fixed tiles meeting
+                             // this range; each computes its rows inside it)
     int32_t b_lo, b_hi;      // buffer rows (empty range: none)
     int32_t ret_lo;          // first of the two retained slow rows next to B
     int32_t use_ret;
@@ -98,7 +99,40 @@ struct ReduceArgs {
     double* final_;          // [2][RED_FIELDS]
 };
 
+// Persistent (dataflow) execution: one launch runs many stages of one or
+// more members.  Each fixed tile of each domain has a progress counter (the
+// last stage it finished); a tile starts stage g once its eight neighbours
+// and, next to the interface, the tile across it have finished g - 1.
+struct TileRef {
+    int32_t member;
+    int32_t dom;       // 0 lower, 1 upper
+    int32_t tx, tz;    // fixed-tile coordinates (TX x TZ, z aligned at multiples of TZ)
+};
+
+struct MemberRun {
+    const StageArgs* stages;   // m*s entries, index (k-1)*s + (j-1)
+    int32_t nstages;           // stages to run in this launch (steps * m * s)
+    int32_t ms;
+    int32_t done_base[2];      // progress-counter index of tile (0, 0) per domain
+    int32_t tiles_x;
+    int32_t tiles_z[2];
+    int32_t pad;
+};
+
+struct PersistArgs {
+    const TileRef* tiles;      // every fixed tile of every member
+    const MemberRun* members;
+    int32_t* done;             // progress counters, zero before the launch
+    int32_t* abort_flag;       // set (never cleared by the kernel) if a wait timed out
+    int32_t ntiles;
+    int32_t gmax;              // largest nstages
+    int64_t wait_ticks;        // longest a task may wait, in wall-clock ticks
+};
+
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
+hipError_t launch_persistent(const PersistArgs& a, int grid, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
+int persistent_blocks_per_cu();
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 
 }  // namespace mprk

@@ -256,9 +256,12 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     const int tid = threadIdx.x;
     const int nx = A.nx, nz = D.nz;
     const int tx = tile % D.tiles_x, tz = tile / D.tiles_x;
+    // Tiles are fixed (TX x TZ, aligned at multiples of TZ in z); a tile
+    // computes its rows inside [row_lo, row_hi): tile rows [vs, ve).
     const int x0 = tx * TX;
-    const int z0 = D.row_lo + tz * TZ;
-    const int nrows = min(TZ, D.row_hi - z0);
+    const int z0 = (D.row_lo / TZ + tz) * TZ;
+    const int vs = max(z0, D.row_lo) - z0;
+    const int ve = min(z0 + TZ, D.row_hi) - z0;
     const int ncols = min(TX, nx - x0);
 
     Lds L;
@@ -269,13 +272,13 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     double* ex_x = lds;                          // [NV][TZ][TX+1]
     double* ex_z = lds + NV * TZ * (TX + 1);     // [NV][TZ+1][TX]
 
-    const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + nrows == nz)
-                                      : (D.gamma_bot && z0 == 0);
+    const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + ve == nz)
+                                      : (D.gamma_bot && z0 + vs == 0);
 
     const int c = tid % TX;
     const int r0 = 2 * (tid / TX);
-    const bool ok0 = (c < ncols) && (r0 < nrows);
-    const bool ok1 = (c < ncols) && (r0 + 1 < nrows);
+    const bool ok0 = (c < ncols) && (r0 >= vs) && (r0 < ve);
+    const bool ok1 = (c < ncols) && (r0 + 1 >= vs) && (r0 + 1 < ve);
 
     // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
     // Each of LOAD_THREADS threads owns one tile column and LOAD_ROWS rows
@@ -362,10 +365,13 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     // z-faces (wave 1), so that no wave runs both directions.
     const int kind2 = (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
     const int kind3 = (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
-    const bool ex_x4 = tid < TZ && tid < nrows;
+    // Edge faces: the x-face left of column 0 on each computed row, and the
+    // z-face below the first computed row (tile row vs - 1 to vs).
+    const bool ex_x4 = tid < TZ && tid >= vs && tid < ve;
     const int ez = tid - 64;
     const bool ex_z4 = ez >= 0 && ez < TX && ez < ncols;
-    const int kind4 = (z0 == 0) ? FACE_BOTTOM : FACE_INTERIOR;
+    const int re = vs - 1;
+    const int kind4 = (z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
     double F[5][NV];
     {
@@ -405,7 +411,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
             for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
         }
         if (ex_z4) {
-            const int c1[1] = {ez}, r1[1] = {-1}, k1[1] = {kind4};
+            const int c1[1] = {ez}, r1[1] = {re}, k1[1] = {kind4};
             face_fluxes<DOM, 1, 1>(A, D, L, c1, r1, k1, Fs);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
@@ -448,7 +454,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     if (ok0) { put_x(c, r0, F[0]); put_z(c, r0, F[2]); }
     if (ok1) { put_x(c, r0 + 1, F[1]); put_z(c, r0 + 1, F[3]); }
     if (ex_x4) put_x(-1, tid, F[4]);
-    if (ex_z4) put_z(ez, -1, F[4]);
+    if (ex_z4) put_z(ez, re, F[4]);
     __syncthreads();
 
     // ---- divergence, source and stage combination
@@ -541,6 +547,102 @@ void stage_kernel(const StageArgs A)
     if (b < n0 || (n0 % 8) == 0) t = xcd_contiguous(t, (b < n0) ? n0 : A.nblocks - n0);
     if (dom == 0) stage_tile<0>(A, t, lds);
     else stage_tile<1>(A, t, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent dataflow kernel.
+// ---------------------------------------------------------------------------
+// Wait until every tile this task reads has finished stage g - 1: the eight
+// neighbours (x periodic) and, next to the interface, the tile across it.
+// Called by the whole of wave 0: lane l < 9 polls neighbour (l%3 - 1, l/3 - 1),
+// lane 9 the interface partner, all in parallel; a wave-wide vote decides.
+// Returns false on timeout or abort; the kernel then exits without
+// finishing (bounded: it never hangs).
+__device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const TileRef& tr, int g)
+{
+    const int need = g - 1;
+    if (need <= 0) return true;
+    const int lane = threadIdx.x & 63;
+    const int tzmax = M.tiles_z[tr.dom] - 1;
+    int dep = -1;
+    if (lane < 9 && lane != 4) {
+        const int dx = lane % 3 - 1, dz = lane / 3 - 1;
+        const int tz = tr.tz + dz;
+        int tx = tr.tx + dx;
+        tx = tx < 0 ? tx + M.tiles_x : (tx >= M.tiles_x ? tx - M.tiles_x : tx);
+        if (tz >= 0 && tz <= tzmax && !(tx == tr.tx && tz == tr.tz))
+            dep = M.done_base[tr.dom] + tz * M.tiles_x + tx;
+    } else if (lane == 9) {
+        if (tr.dom == 0 && tr.tz == tzmax) dep = M.done_base[1] + tr.tx;
+        if (tr.dom == 1 && tr.tz == 0) dep = M.done_base[0] + (M.tiles_z[0] - 1) * M.tiles_x + tr.tx;
+    }
+    const int64_t t0 = wall_clock64();
+    while (true) {
+        const bool ready = dep < 0 ||
+            __hip_atomic_load(P.done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        if (__all(ready)) break;
+        __builtin_amdgcn_s_sleep(1);
+        const bool ab = lane == 0 &&
+            __hip_atomic_load(P.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (__any(ab) || wall_clock64() - t0 > P.wait_ticks) {
+            if (lane == 0) __hip_atomic_store(P.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    // Make the producers' stores visible to this workgroup's loads.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+#ifndef MPRK_PERSIST_WAVES_PER_EU
+#define MPRK_PERSIST_WAVES_PER_EU 2
+#endif
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_PERSIST_WAVES_PER_EU)))
+void persistent_kernel(const PersistArgs P)
+{
+    __shared__ double lds[LDS_N];
+    __shared__ int s_go;
+    const int G = gridDim.x;
+    for (int g = 1; g <= P.gmax; ++g) {
+        // Blocks j and j + G run on the same XCD when G % 8 == 0; the remap
+        // gives each XCD a contiguous range of tiles.
+        for (int i = blockIdx.x; i < P.ntiles; i += G) {
+            const int t = (G % 8 == 0) ? xcd_contiguous(i, P.ntiles) : i;
+            const TileRef tr = P.tiles[t];
+            const MemberRun& M = P.members[tr.member];
+            if (g > M.nstages) continue;
+            const StageArgs& A = M.stages[(g - 1) % M.ms];
+            const DomainArgs& D = A.d[tr.dom];
+            const int z0 = tr.tz * TZ;
+            const bool work = D.row_hi > D.row_lo && z0 < D.row_hi && z0 + TZ > D.row_lo;
+            if (work) {
+                if (threadIdx.x < 64) {
+                    const bool ok = wait_inputs(P, M, tr, g);
+                    if (threadIdx.x == 0) s_go = ok ? 1 : 0;
+                }
+                __syncthreads();
+                if (!s_go) return;
+                const int rel = (tr.tz - D.row_lo / TZ) * D.tiles_x + tr.tx;
+                if (tr.dom == 0) stage_tile<0>(A, rel, lds);
+                else stage_tile<1>(A, rel, lds);
+                // Every wave's stores are complete before thread 0 publishes.
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(P.done + M.done_base[tr.dom] + tr.tz * M.tiles_x + tr.tx, g,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+__global__ void fill_i32(int32_t* p, int32_t v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -659,6 +761,27 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s)
     if (a.nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(stage_kernel, dim3(a.nblocks), dim3(NT), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_persistent(const PersistArgs& a, int grid, hipStream_t s)
+{
+    void* args[] = {(void*)&a};
+    return hipLaunchCooperativeKernel((const void*)persistent_kernel, dim3(grid), dim3(NT), args, 0, s);
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)persistent_kernel, NT, 0) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s)

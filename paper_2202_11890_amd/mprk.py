@@ -11,7 +11,8 @@ import ctypes
 import os
 
 ABI_VERSION = 1
-OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+EXEC_LAUNCH, EXEC_PERSISTENT = 0, 1
 REGION_F, REGION_B, REGION_S, REGION_ALL = 1, 2, 4, 7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -77,8 +78,9 @@ class mprk_stats(ctypes.Structure):
 
 
 EXPORTS = ("mprk_validate", "mprk_workspace_bytes", "mprk_create", "mprk_set_stream", "mprk_rhs",
-           "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_stable_dt", "mprk_profile_enable",
-           "mprk_profile_take", "mprk_destroy", "mprk_strerror")
+           "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_stable_dt", "mprk_set_exec",
+           "mprk_set_wait_limit",
+           "mprk_profile_enable", "mprk_profile_take", "mprk_destroy", "mprk_strerror")
 
 _lib = None
 
@@ -111,6 +113,8 @@ def load(path: str = LIB_PATH):
     lib.mprk_diagnostics.argtypes = [V, S]
     lib.mprk_stable_dt.argtypes = [C, S, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_double)]
+    lib.mprk_set_exec.argtypes = [V, ctypes.c_int]
+    lib.mprk_set_wait_limit.argtypes = [V, ctypes.c_double]
     lib.mprk_profile_enable.argtypes = [V, ctypes.c_int]
     lib.mprk_profile_take.argtypes = [V, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
@@ -173,6 +177,14 @@ def mprk_stable_dt(cfg, st, cr, dn):
     return rc, dt.value
 
 
+def mprk_set_exec(ctx, mode):
+    return load().mprk_set_exec(ctx, int(mode))
+
+
+def mprk_set_wait_limit(ctx, seconds):
+    return load().mprk_set_wait_limit(ctx, float(seconds))
+
+
 def mprk_profile_enable(ctx, on):
     return load().mprk_profile_enable(ctx, int(bool(on)))
 
@@ -214,7 +226,7 @@ class Solver:
     """Owns the workspace tensor and the context; the state tensors belong to
     the caller and are updated in place."""
 
-    def __init__(self, cfg: mprk_config, q_lower, q_upper, stream=None):
+    def __init__(self, cfg: mprk_config, q_lower, q_upper, stream=None, exec_mode=None):
         import torch
 
         for t in (q_lower, q_upper):
@@ -236,6 +248,8 @@ class Solver:
         rc, self.ctx = mprk_create(cfg, q_lower.data_ptr(), q_upper.data_ptr(), self._ws_ptr,
                                    nbytes, self.stream.cuda_stream)
         _check(rc, "mprk_create")
+        if exec_mode is not None:
+            self.set_exec(exec_mode)
 
     def rhs(self, q_lower, q_upper, r_lower, r_upper, mask=REGION_ALL):
         _check(mprk_rhs(self.ctx, q_lower.data_ptr(), q_upper.data_ptr(), r_lower.data_ptr(),
@@ -261,6 +275,12 @@ class Solver:
         rc, dt = mprk_stable_dt(self.cfg, st, cr, dn)
         _check(rc, "mprk_stable_dt")
         return dt
+
+    def set_exec(self, mode: int):
+        _check(mprk_set_exec(self.ctx, mode), "mprk_set_exec")
+
+    def set_wait_limit(self, seconds: float):
+        _check(mprk_set_wait_limit(self.ctx, seconds), "mprk_set_wait_limit")
 
     def profile(self, on: bool):
         _check(mprk_profile_enable(self.ctx, on), "mprk_profile_enable")
