@@ -36,11 +36,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--check-every", type=int, default=10)
-    ap.add_argument("--exec", choices=["persistent", "launch"], default="persistent",
+    ap.add_argument("--exec", choices=["persistent", "launch"], default="launch",
                     help="persistent: one cooperative launch per check segment; launch: one per stage")
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux run")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -234,6 +235,33 @@ def main():
         "roofline": roofline,
     }
     sol.close()
+
+    # ---- the same run with FP32 face fluxes (state and sums in FP64)
+    if not args.no_fp32:
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        f32 = mprk.Solver(mprk.config_of_workload(w, flux_bits=32), tl, tu, exec_mode=exec_mode)
+        f32.run(dt, max(W, 1), check_every=0)
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fst = f32.run(dt, K, check_every=args.check_every)
+        torch.cuda.synchronize()
+        t_32 = time.perf_counter() - t0
+        f32.close()
+        dif = []
+        for g, r in zip((tl.cpu().numpy(), tu.cpu().numpy()), mprk_final):
+            scale = np.abs(r).max(axis=(1, 2))
+            scale[1:3] = max(scale[1], scale[2])
+            dif.append((np.abs(g - r).max(axis=(1, 2)) / scale).tolist())
+        out["fp32_flux"] = {
+            "value": cs_step * K / t_32, "ms_per_step": 1e3 * t_32 / K, "status": fst["status"],
+            "speedup_vs_f64": t_mprk / t_32,
+            "max_rel_diff_vs_f64": {"lower": dif[0], "upper": dif[1]},
+        }
+        print("# fp32 flux: %.1f us/step, speedup %.3f" % (1e6 * t_32 / K, t_mprk / t_32),
+              file=sys.stderr, flush=True)
 
     # ---- single-rate RK at the fast step on the same GPU
     if not args.no_sr:

@@ -205,8 +205,10 @@ int mprk_validate(const mprk_config* c, char* msg, size_t len)
         return MPRK_EINVAL;
     }
     if (!std::isfinite(c->gravity)) { set_msg(msg, len, "gravity must be finite"); return MPRK_EINVAL; }
-    if (c->flux_bits == 32) { set_msg(msg, len, "flux_bits 32 is not implemented"); return MPRK_EUNSUPPORTED; }
-    if (c->flux_bits != 64) { set_msg(msg, len, "flux_bits must be 64"); return MPRK_EINVAL; }
+    if (c->flux_bits != 64 && c->flux_bits != 32) {
+        set_msg(msg, len, "flux_bits must be 64 or 32");
+        return MPRK_EINVAL;
+    }
     const int s = c->base_rk;
     if (c->m > 1 && c->n_buffer < 2 * s - 1) {
         if (c->strict_buffer) {
@@ -325,6 +327,7 @@ StageArgs base_args(const mprk_ctx* c)
     a.bT = 2.0 * k1 * k2 / (dz2 * k1 + dz1 * k2);
     a.half_dz1_mu1 = dz1 / (2.0 * mu1);
     a.inv_m = 1.0 / g.m;
+    a.flux32 = g.flux_bits == 32 ? 1 : 0;
     for (int d = 0; d < 2; ++d) {
         DomainArgs& D = a.d[d];
         D.nz = d == 0 ? g.nz_lower : g.nz_upper;
@@ -510,7 +513,7 @@ int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
         int coop = 0;
         if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
             return MPRK_EUNSUPPORTED;
-        const int per_cu = persistent_blocks_per_cu();
+        const int per_cu = persistent_blocks_per_cu(g.flux_bits == 32);
         if (per_cu <= 0) return MPRK_EHIP;
         int grid = per_cu * prop.multiProcessorCount;
         if (grid > c->lay.ntiles) grid = c->lay.ntiles;
@@ -572,7 +575,7 @@ int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
     P.ntiles = c->lay.ntiles;
     P.gmax = mr.nstages;
     P.wait_ticks = c->wait_ticks;
-    if (launch_persistent(P, c->pgrid, c->stream) != hipSuccess) return MPRK_EHIP;
+    if (launch_persistent(P, c->pgrid, g.flux_bits == 32, c->stream) != hipSuccess) return MPRK_EHIP;
     return MPRK_OK;
 }
 

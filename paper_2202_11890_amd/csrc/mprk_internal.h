@@ -75,7 +75,7 @@ struct StageArgs {
     int32_t nx;
     int32_t nblocks;         // d[0].ntiles + d[1].ntiles
     int32_t first;           // domain whose tiles take the first blocks
-    int32_t pad0;
+    int32_t flux32;          // 1: face fluxes in FP32 (state, stage sums, interface flux FP64)
     double dx, inv_dx;
     double gamma, gm1, gravity;
     double bu, bT;           // bulk coefficients of the interface flux
@@ -130,9 +130,9 @@ struct PersistArgs {
 };
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-hipError_t launch_persistent(const PersistArgs& a, int grid, hipStream_t s);
+hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
-int persistent_blocks_per_cu();
+int persistent_blocks_per_cu(bool flux32);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 
 }  // namespace mprk

@@ -23,30 +23,19 @@ namespace mprk {
 
 namespace {
 
-#ifndef MPRK_FACE_PAIRS
-#define MPRK_FACE_PAIRS 0
-#endif
-// Keep face evaluations from being interleaved by the scheduler: the
-// interleaved form needs far more registers than the occupancy allows.
-#ifndef MPRK_FACE_SEQ
-#define MPRK_FACE_SEQ 0
-#endif
-#if MPRK_FACE_SEQ
-#define FACE_SCHED_BARRIER() __builtin_amdgcn_sched_barrier(0)
-#else
-#define FACE_SCHED_BARRIER() ((void)0)
-#endif
-
 constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
 constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
-constexpr int LDS_G = 2 * TX;              // u, T of the cell across the interface
-constexpr int LDS_O = NV * TX;             // conserved state of that cell
 constexpr int LDS_EX = NV * TZ * (TX + 1) + NV * (TZ + 1) * TX;  // face fluxes
-constexpr int LDS_N = LDS_Q + LDS_P + LDS_G + LDS_O;
 static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
 constexpr int LOAD_RG = NT / HX;                        // row groups of the loader
 constexpr int LOAD_THREADS = LOAD_RG * HX;
 constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG; // rows per loader thread
+
+// Shared memory of one tile: the staged state and primitives in the flux
+// type FT (the flux exchange reuses that space), then the per-column
+// interface flux in FP64.
+template <class FT>
+constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 2 * TX * 8; }
 
 __device__ __forceinline__ int wrapx(int c, int nx)
 {
@@ -65,11 +54,6 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(0.5 * y, r, y);
 }
 
-// sqrt(x) = x / sqrt(x) for positive normal x (no scaling for subnormals,
-// zero or infinity, which a physical state never produces; a non-physical
-// one yields NaN, which the device status check reports).
-__device__ __forceinline__ double sqrt_nr(double x) { return x * rsqrt_nr(x); }
-
 // 1/x for positive normal x: hardware estimate refined by two Newton steps
 // y <- y + y (1 - x y).
 __device__ __forceinline__ double rcp_nr(double x)
@@ -79,26 +63,53 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(y, fma(-x, y, 1.0), y);
 }
 
-// Cell primitives.  Contraction is off so that the value is identical
-// wherever it is evaluated: the interface flux is computed on both sides of
-// the interface and must agree to the bit for conservation.
-__device__ __forceinline__ void primitives(double rho, double mx, double mz, double en,
-                                           double gamma, double gm1, double& u, double& w,
-                                           double& T)
+// Reciprocal, square root and reciprocal square root of positive normal
+// arguments in the flux type.  FP64: hardware estimates refined by Newton
+// steps (a few ulp).  FP32: the hardware instructions (1 ulp).  No scaling
+// for subnormals, zero or infinity, which a physical state never produces; a
+// non-physical one yields NaN, which the device status check reports.
+template <class FT> struct Fm;
+template <> struct Fm<double> {
+    static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return rsqrt_nr(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return x * rsqrt_nr(x); }
+};
+template <> struct Fm<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// Cell primitives u, w, T in the flux type (staged for the viscous fluxes).
+template <class FT>
+__device__ __forceinline__ void primitives(FT rho, FT mx, FT mz, FT en, FT gamma, FT gm1, FT& u,
+                                           FT& w, FT& T)
+{
+    const FT ir = Fm<FT>::rcp(rho);
+    u = mx * ir;
+    w = mz * ir;
+    const FT p = gm1 * (en - FT(0.5) * (mx * u + mz * w));
+    T = gamma * p * ir;
+}
+
+// FP64 u and T of a cell next to the interface.  Contraction is off and the
+// same code runs in the tiles on both sides, so both obtain the same bits.
+__device__ __forceinline__ void interface_cell(double rho, double mx, double mz, double en,
+                                               double gamma, double gm1, double& u, double& T)
 {
 #pragma clang fp contract(off)
     const double ir = rcp_nr(rho);
     u = mx * ir;
-    w = mz * ir;
-    double p = gm1 * (en - 0.5 * (mx * u + mz * w));
+    const double w = mz * ir;
+    const double p = gm1 * (en - 0.5 * (mx * u + mz * w));
     T = gamma * p * ir;
 }
 
 // Interface viscous flux in +z (Appendix B, eq. bulk-flux; hat w = 0 and
 // hat sigma_zz = 0 on the lid): (0, sigma_xz, 0, u_w sigma_xz - Pi_z) with
 // sigma_xz = b_u (u2 - u1), Pi_z = -b_T (T2 - T1), u_w = u1 + sigma dz1/(2 mu1).
-// Index 1 is the lower cell, 2 the upper cell.  Contraction off: both domains
-// evaluate it and must obtain the same bits.
+// Index 1 is the lower cell, 2 the upper cell.  FP64, contraction off: both
+// domains evaluate it and must obtain the same bits (exact exchange).
 __device__ __forceinline__ void interface_flux(const StageArgs& A, double u1, double T1,
                                                double u2, double T2, double& f1, double& f3)
 {
@@ -110,11 +121,11 @@ __device__ __forceinline__ void interface_flux(const StageArgs& A, double u1, do
     f3 = uw * sig - pi;
 }
 
+template <class FT>
 struct Lds {
-    double* q;   // [NV][HZ][HX]
-    double* p;   // [3][PZ][PX]
-    double* g;   // [2][TX]
-    double* o;   // [NV][TX]
+    FT* q;        // [NV][HZ][HX]
+    FT* p;        // [3][PZ][PX]
+    double* gf;   // [2][TX]: interface flux (x-momentum, energy) per column
 };
 
 __device__ __forceinline__ int qidx(int v, int r, int c) { return (v * HZ + r + 2) * HX + c + 2; }
@@ -125,20 +136,23 @@ enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
 
 // Numerical flux (inviscid minus viscous) through the face between tile cell
 // (c, r) and its +dir neighbour, in the face-normal frame: returns
-// (F_rho, F_normal-momentum, F_tangential-momentum, F_energy).
+// (F_rho, F_normal-momentum, F_tangential-momentum, F_energy), in FT.
 //   kind FACE_TOP:    (c, r) is the top interior row; the other side is its
-//                     mirror; gam = interface above.
-//   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; gam = interface
-//                     below.
-// For a wall the viscous flux is zero; at the interface it is the bulk flux.
-// N independent faces are evaluated in lockstep so that their dependency
-// chains interleave.
-template <int DOM, int dir, int N>
-__device__ __forceinline__ void face_fluxes(const StageArgs& A, const DomainArgs& D, const Lds& L,
-                                            const int (&c)[N], const int (&r)[N],
-                                            const int (&kind)[N], double (&F)[N][NV])
+//                     mirror (wall or interface).
+//   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; likewise.
+// At walls and at the interface the viscous part is not added here: walls
+// carry none, and the interface flux enters the divergence in FP64.
+template <class FT, int dir>
+__device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& D, const Lds<FT>& L,
+                                          int c, int r, int kind, FT F[NV])
 {
-    const double gamma = A.gamma, gm1 = A.gm1;
+    // A face on a tile edge is computed by the tiles on both sides, at
+    // different call sites.  With contraction off and the fused operations
+    // written out, every call site performs the same IEEE operations, so both
+    // obtain the same bits and the flux differences telescope exactly.
+#pragma clang fp contract(off)
+    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT h = FT(0.5), q4 = FT(0.25);
     constexpr int sn = dir ? HX : 1;         // normal stride in the state tile
     constexpr int vn = dir ? 2 : 1;          // normal momentum component
     constexpr int vt = dir ? 1 : 2;          // tangential momentum component
@@ -147,109 +161,89 @@ __device__ __forceinline__ void face_fluxes(const StageArgs& A, const DomainArgs
 
     // Reconstruction of conserved variables with central cell gradients:
     // qL = q_c + (q_{c+1} - q_{c-1})/4, qR = q_{c+1} - (q_{c+2} - q_c)/4.
-    double qL[N][NV], qR[N][NV];
+    FT qL[NV], qR[NV];
+    const int base = qidx(0, r, c);
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const int base = qidx(0, r[n], c[n]);
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double* s = L.q + comp[k] * plane + base;
-            const double qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
-            qL[n][k] = q0 + 0.25 * (q1 - qm);
-            qR[n][k] = q1 - 0.25 * (q2 - q0);
-        }
-        if (kind[n] == FACE_TOP) {
-            qR[n][0] = qL[n][0]; qR[n][1] = -qL[n][1]; qR[n][2] = qL[n][2]; qR[n][3] = qL[n][3];
-        } else if (kind[n] == FACE_BOTTOM) {
-            qL[n][0] = qR[n][0]; qL[n][1] = -qR[n][1]; qL[n][2] = qR[n][2]; qL[n][3] = qR[n][3];
-        }
+    for (int k = 0; k < NV; ++k) {
+        const FT* s = L.q + comp[k] * plane + base;
+        const FT qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
+        qL[k] = fma(q4, q1 - qm, q0);
+        qR[k] = fma(-q4, q2 - q0, q1);
+    }
+    if (kind == FACE_TOP) {
+        qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3];
+    } else if (kind == FACE_BOTTOM) {
+        qL[0] = qR[0]; qL[1] = -qR[1]; qL[2] = qR[2]; qL[3] = qR[3];
     }
 
     // Local Lax-Friedrichs flux, lambda = max(|u_n| + a) over qL, qR and the
     // Roe average (sqrt(rho)-weighted velocity and total enthalpy).  One
     // reciprocal square root per side gives 1/rho and sqrt(rho).
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const double* l = qL[n];
-        const double* q = qR[n];
-        const double yL = rsqrt_nr(l[0]), yR = rsqrt_nr(q[0]);
-        const double rL = yL * yL, rR = yR * yR;
-        const double sL = l[0] * yL, sR = q[0] * yR;
-        const double unL = l[1] * rL, utL = l[2] * rL;
-        const double unR = q[1] * rR, utR = q[2] * rR;
-        const double pL = gm1 * (l[3] - 0.5 * (l[1] * unL + l[2] * utL));
-        const double pR = gm1 * (q[3] - 0.5 * (q[1] * unR + q[2] * utR));
-        const double aL = sqrt_nr(gamma * pL * rL);
-        const double aR = sqrt_nr(gamma * pR * rR);
-        const double iw = rcp_nr(sL + sR);
-        const double unr = (sL * unL + sR * unR) * iw;
-        const double utr = (sL * utL + sR * utR) * iw;
-        const double HL = (l[3] + pL) * rL, HR = (q[3] + pR) * rR;
-        const double Hr = (sL * HL + sR * HR) * iw;
-        const double ar = sqrt_nr(gm1 * (Hr - 0.5 * (unr * unr + utr * utr)));
-        const double lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
-        const double hl = 0.5 * lam;
-        F[n][0] = 0.5 * (l[1] + q[1]) - hl * (q[0] - l[0]);
-        F[n][1] = 0.5 * (l[1] * unL + q[1] * unR + pL + pR) - hl * (q[1] - l[1]);
-        F[n][2] = 0.5 * (l[2] * unL + q[2] * unR) - hl * (q[2] - l[2]);
-        F[n][3] = 0.5 * ((l[3] + pL) * unL + (q[3] + pR) * unR) - hl * (q[3] - l[3]);
+    const FT yL = Fm<FT>::rsqrt(qL[0]), yR = Fm<FT>::rsqrt(qR[0]);
+    const FT rL = yL * yL, rR = yR * yR;
+    const FT sL = qL[0] * yL, sR = qR[0] * yR;
+    const FT unL = qL[1] * rL, utL = qL[2] * rL;
+    const FT unR = qR[1] * rR, utR = qR[2] * rR;
+    const FT pL = gm1 * fma(-h, fma(qL[1], unL, qL[2] * utL), qL[3]);
+    const FT pR = gm1 * fma(-h, fma(qR[1], unR, qR[2] * utR), qR[3]);
+    const FT aL = Fm<FT>::sqrt(gamma * pL * rL);
+    const FT aR = Fm<FT>::sqrt(gamma * pR * rR);
+    const FT iw = Fm<FT>::rcp(sL + sR);
+    const FT unr = fma(sL, unL, sR * unR) * iw;
+    const FT utr = fma(sL, utL, sR * utR) * iw;
+    const FT HL = (qL[3] + pL) * rL, HR = (qR[3] + pR) * rR;
+    const FT Hr = fma(sL, HL, sR * HR) * iw;
+    const FT ar = Fm<FT>::sqrt(gm1 * fma(-h, fma(unr, unr, utr * utr), Hr));
+    const FT lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
+    if (kind != FACE_INTERIOR) {
+        // Against its mirror image the flux reduces exactly to
+        // (0, rho u_n^2 + p +- lambda rho u_n, 0, 0); the closed form keeps
+        // the mass, tangential-momentum and energy fluxes at exactly zero,
+        // where the general formula leaves rounding residuals.
+        F[0] = FT(0);
+        F[1] = (kind == FACE_TOP) ? fma(lam, qL[1], fma(qL[1], unL, pL))
+                                  : fma(-lam, qR[1], fma(qR[1], unR, pR));
+        F[2] = FT(0);
+        F[3] = FT(0);
+        return;
     }
+    const FT hl = h * lam;
+    F[0] = fma(-hl, qR[0] - qL[0], h * (qL[1] + qR[1]));
+    F[1] = fma(-hl, qR[1] - qL[1], h * (fma(qL[1], unL, qR[1] * unR) + (pL + pR)));
+    F[2] = fma(-hl, qR[2] - qL[2], h * fma(qL[2], unL, qR[2] * unR));
+    F[3] = fma(-hl, qR[3] - qL[3], h * fma(qL[3] + pL, unL, (qR[3] + pR) * unR));
 
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        if (kind[n] == FACE_INTERIOR) {
-            // Common values: averaged velocity, normal derivative by finite
-            // difference, tangential derivative by averaging cell gradients.
-            const int pb = pidx(0, r[n], c[n]);
-            constexpr int pn = dir ? PX : 1;
-            constexpr int pt = dir ? 1 : PX;
-            constexpr int fn = dir ? 1 : 0;  // normal velocity in the primitive tile
-            constexpr int ft = dir ? 0 : 1;
-            constexpr int pp = PZ * PX;
-            const double* Un = L.p + fn * pp + pb;
-            const double* Ut = L.p + ft * pp + pb;
-            const double* Tt = L.p + 2 * pp + pb;
-            const double inv_n = dir ? D.inv_dz : A.inv_dx;
-            const double inv_t4 = 0.25 * (dir ? A.inv_dx : D.inv_dz);
-            const double unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
-            const double dn_un = (unB - unA) * inv_n;
-            const double dn_ut = (utB - utA) * inv_n;
-            const double dn_T = (Tt[pn] - Tt[0]) * inv_n;
-            const double dt_un = (Un[pt] - Un[-pt] + Un[pn + pt] - Un[pn - pt]) * inv_t4;
-            const double dt_ut = (Ut[pt] - Ut[-pt] + Ut[pn + pt] - Ut[pn - pt]) * inv_t4;
-            const double mu = D.mu;
-            const double snn = mu * ((4.0 / 3.0) * dn_un - (2.0 / 3.0) * dt_ut);
-            const double snt = mu * (dn_ut + dt_un);
-            F[n][1] -= snn;
-            F[n][2] -= snt;
-            F[n][3] -= 0.5 * (unA + unB) * snn + 0.5 * (utA + utB) * snt + D.kappa * dn_T;
-        } else {
-            const bool gam = (kind[n] == FACE_TOP) ? D.gamma_top : D.gamma_bot;
-            if (gam) {
-                // Only z-faces reach here: normal = w, tangential = u.
-                double u1, T1, u2, T2;
-                if (DOM == 0) {   // interface above the lower domain's top row r
-                    u1 = L.p[pidx(0, r[n], c[n])];
-                    T1 = L.p[pidx(2, r[n], c[n])];
-                    u2 = L.g[c[n]];
-                    T2 = L.g[TX + c[n]];
-                } else {          // interface below the upper domain's bottom row r+1
-                    u1 = L.g[c[n]];
-                    T1 = L.g[TX + c[n]];
-                    u2 = L.p[pidx(0, r[n] + 1, c[n])];
-                    T2 = L.p[pidx(2, r[n] + 1, c[n])];
-                }
-                double f1, f3;
-                interface_flux(A, u1, T1, u2, T2, f1, f3);
-                F[n][2] -= f1;   // tangential momentum (x) component
-                F[n][3] -= f3;
-            }
-        }
+    {
+        // Common values: averaged velocity, normal derivative by finite
+        // difference, tangential derivative by averaging cell gradients.
+        const int pb = pidx(0, r, c);
+        constexpr int pn = dir ? PX : 1;
+        constexpr int pt = dir ? 1 : PX;
+        constexpr int fn = dir ? 1 : 0;      // normal velocity in the primitive tile
+        constexpr int ft = dir ? 0 : 1;
+        constexpr int pp = PZ * PX;
+        const FT* Un = L.p + fn * pp + pb;
+        const FT* Ut = L.p + ft * pp + pb;
+        const FT* Tt = L.p + 2 * pp + pb;
+        const FT inv_n = FT(dir ? D.inv_dz : A.inv_dx);
+        const FT inv_t4 = FT(0.25 * (dir ? A.inv_dx : D.inv_dz));
+        const FT unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
+        const FT dn_un = (unB - unA) * inv_n;
+        const FT dn_ut = (utB - utA) * inv_n;
+        const FT dn_T = (Tt[pn] - Tt[0]) * inv_n;
+        const FT dt_un = ((Un[pt] - Un[-pt]) + (Un[pn + pt] - Un[pn - pt])) * inv_t4;
+        const FT dt_ut = ((Ut[pt] - Ut[-pt]) + (Ut[pn + pt] - Ut[pn - pt])) * inv_t4;
+        const FT mu = FT(D.mu);
+        const FT snn = mu * fma(FT(4.0 / 3.0), dn_un, FT(-2.0 / 3.0) * dt_ut);
+        const FT snt = mu * (dn_ut + dt_un);
+        F[1] = F[1] - snn;
+        F[2] = F[2] - snt;
+        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, FT(D.kappa) * dn_T));
     }
 }
 
-template <int DOM>
-__device__ void stage_tile(const StageArgs& A, int tile, double* lds)
+template <int DOM, class FT>
+__device__ void stage_tile(const StageArgs& A, int tile, char* smem)
 {
     const DomainArgs& D = A.d[DOM];
     const DomainArgs& O = A.d[1 - DOM];
@@ -264,14 +258,15 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     const int ve = min(z0 + TZ, D.row_hi) - z0;
     const int ncols = min(TX, nx - x0);
 
-    Lds L;
-    L.q = lds;
-    L.p = lds + LDS_Q;
-    L.g = L.p + LDS_P;
-    L.o = L.g + LDS_G;
-    double* ex_x = lds;                          // [NV][TZ][TX+1]
-    double* ex_z = lds + NV * TZ * (TX + 1);     // [NV][TZ+1][TX]
+    Lds<FT> L;
+    L.q = (FT*)smem;
+    L.p = L.q + LDS_Q;
+    L.gf = (double*)(smem + (LDS_Q + LDS_P) * sizeof(FT));
+    FT* ex_x = L.q;                              // [NV][TZ][TX+1]
+    FT* ex_z = L.q + NV * TZ * (TX + 1);         // [NV][TZ+1][TX]
 
+    // The interface is above this tile's last computed row (lower domain) or
+    // below its first (upper domain).
     const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + ve == nz)
                                       : (D.gamma_bot && z0 + vs == 0);
 
@@ -317,17 +312,28 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
             if (zr < HZ) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    L.q[(v * HZ + zr) * HX + xc] = (v == 2 && neg[k]) ? -val[k][v] : val[k][v];
+                    L.q[(v * HZ + zr) * HX + xc] = FT((v == 2 && neg[k]) ? -val[k][v] : val[k][v]);
             }
         }
     }
-    if (has_gamma) {
-        const int orow = (DOM == 0) ? 0 : O.nz - 1;
-        for (int i = tid; i < NV * TX; i += NT) {
-            const int v = i / TX, c = i - v * TX;
-            const int col = wrapx(x0 + c, nx);
-            L.o[i] = O.qin[((size_t)v * O.nz + orow) * nx + col];
-        }
+    // Interface flux per column, FP64, from the FP64 cell averages of the two
+    // cells next to the interface (the tiles on both sides compute the same
+    // bits).
+    if (has_gamma && tid < TX) {
+        const int col = wrapx(x0 + tid, nx);
+        const int own = (DOM == 0) ? nz - 1 : 0;
+        const int oth = (DOM == 0) ? 0 : O.nz - 1;
+        const size_t po = (size_t)nz * nx, pq = (size_t)O.nz * nx;
+        const double* a = D.qin + (size_t)own * nx + col;
+        const double* b = O.qin + (size_t)oth * nx + col;
+        double ua, Ta, ub, Tb;
+        interface_cell(a[0], a[po], a[2 * po], a[3 * po], A.gamma, A.gm1, ua, Ta);
+        interface_cell(b[0], b[pq], b[2 * pq], b[3 * pq], A.gamma, A.gm1, ub, Tb);
+        double f1, f3;
+        if (DOM == 0) interface_flux(A, ua, Ta, ub, Tb, f1, f3);
+        else interface_flux(A, ub, Tb, ua, Ta, f1, f3);
+        L.gf[tid] = f1;
+        L.gf[TX + tid] = f3;
     }
     __syncthreads();
 
@@ -335,95 +341,42 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     for (int idx = tid; idx < PZ * PX; idx += NT) {
         const int pr = idx / PX, pc = idx - pr * PX;
         const int b = qidx(0, pr - 1, pc - 1);
-        double u, w, T;
-        primitives(L.q[b], L.q[b + HZ * HX], L.q[b + 2 * HZ * HX], L.q[b + 3 * HZ * HX],
-                   A.gamma, A.gm1, u, w, T);
+        FT u, w, T;
+        primitives<FT>(L.q[b], L.q[b + HZ * HX], L.q[b + 2 * HZ * HX], L.q[b + 3 * HZ * HX],
+                       FT(A.gamma), FT(A.gm1), u, w, T);
         L.p[idx] = u;
         L.p[PZ * PX + idx] = w;
         L.p[2 * PZ * PX + idx] = T;
     }
-    if (has_gamma && tid < TX) {
-        double u, w, T;
-        primitives(L.o[tid], L.o[TX + tid], L.o[2 * TX + tid], L.o[3 * TX + tid], A.gamma,
-                   A.gm1, u, w, T);
-        L.g[tid] = u;
-        L.g[TX + tid] = T;
-    }
     __syncthreads();
 
-    // ---- faces
-
-    double qc[2][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        qc[0][v] = L.q[qidx(v, r0, c)];
-        qc[1][v] = L.q[qidx(v, r0 + 1, c)];
-    }
-
-    // Slots 0,1: x-faces right of the two cells; 2,3: z-faces above them;
-    // 4: the tile's left column of x-faces (wave 0) and bottom row of
-    // z-faces (wave 1), so that no wave runs both directions.
+    // ---- faces.  Slots 0,1: x-faces right of the two cells; 2,3: z-faces
+    // above them; 4: the x-face left of column 0 on each computed row (wave 0)
+    // and the z-face below the first computed row (wave 1), so that no wave
+    // runs both directions.
     const int kind2 = (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
     const int kind3 = (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
-    // Edge faces: the x-face left of column 0 on each computed row, and the
-    // z-face below the first computed row (tile row vs - 1 to vs).
     const bool ex_x4 = tid < TZ && tid >= vs && tid < ve;
     const int ez = tid - 64;
     const bool ex_z4 = ez >= 0 && ez < TX && ez < ncols;
     const int re = vs - 1;
     const int kind4 = (z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
-    double F[5][NV];
-    {
-        const int cx[2] = {c, c}, rx[2] = {r0, r0 + 1};
-        const int kx[2] = {FACE_INTERIOR, FACE_INTERIOR}, kz[2] = {kind2, kind3};
-#if MPRK_FACE_PAIRS
-        double Fp[2][NV];
-        if (ok0 || ok1) {
-            face_fluxes<DOM, 0, 2>(A, D, L, cx, rx, kx, Fp);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) { F[0][v] = Fp[0][v]; F[1][v] = Fp[1][v]; }
-            face_fluxes<DOM, 1, 2>(A, D, L, cx, rx, kz, Fp);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) { F[2][v] = Fp[0][v]; F[3][v] = Fp[1][v]; }
-        }
-#else
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (!(h ? ok1 : ok0)) continue;
-            const int c1[1] = {c}, r1[1] = {rx[h]}, k1[1] = {FACE_INTERIOR}, k2[1] = {kz[h]};
-            double Fs[1][NV];
-            face_fluxes<DOM, 0, 1>(A, D, L, c1, r1, k1, Fs);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) F[h][v] = Fs[0][v];
-            FACE_SCHED_BARRIER();
-            face_fluxes<DOM, 1, 1>(A, D, L, c1, r1, k2, Fs);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) F[2 + h][v] = Fs[0][v];
-            FACE_SCHED_BARRIER();
-        }
-#endif
-        double Fs[1][NV];
-        if (ex_x4) {
-            const int c1[1] = {-1}, r1[1] = {tid}, k1[1] = {FACE_INTERIOR};
-            face_fluxes<DOM, 0, 1>(A, D, L, c1, r1, k1, Fs);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
-        }
-        if (ex_z4) {
-            const int c1[1] = {ez}, r1[1] = {re}, k1[1] = {kind4};
-            face_fluxes<DOM, 1, 1>(A, D, L, c1, r1, k1, Fs);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) F[4][v] = Fs[0][v];
-        }
-    }
+    FT F[5][NV];
+    if (ok0) face_flux<FT, 0>(A, D, L, c, r0, FACE_INTERIOR, F[0]);
+    if (ok1) face_flux<FT, 0>(A, D, L, c, r0 + 1, FACE_INTERIOR, F[1]);
+    if (ok0) face_flux<FT, 1>(A, D, L, c, r0, kind2, F[2]);
+    if (ok1) face_flux<FT, 1>(A, D, L, c, r0 + 1, kind3, F[3]);
+    if (ex_x4) face_flux<FT, 0>(A, D, L, -1, tid, FACE_INTERIOR, F[4]);
+    if (ex_z4) face_flux<FT, 1>(A, D, L, ez, re, kind4, F[4]);
 
-    // Pointwise global reads of the substep base U for the combination; they
-    // complete while the fluxes are exchanged.
+    // Pointwise FP64 reads for the combination (the stage value itself when
+    // the fluxes are FP32, and the substep base U); they complete while the
+    // fluxes are exchanged.
     const int col = x0 + c;
     const size_t plane = (size_t)nz * nx;
     const size_t nbx = (size_t)(D.b_hi - D.b_lo) * nx;
-    double Ub[2][NV];
+    double qc[2][NV], Ub[2][NV];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int row = z0 + r0 + h;
@@ -432,7 +385,17 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
         const Combine& cb = inb ? D.buf : D.main;
         const size_t id = (size_t)row * nx + col;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Ub[h][v] = 0.0;
+        for (int v = 0; v < NV; ++v) {
+            Ub[h][v] = 0.0;
+            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx(v, r0 + h, c)] : 0.0;
+        }
+        if (ok && sizeof(FT) != 8) {
+            // Stage values of this tile's own rows come from the state or the
+            // stage array (never from the retained rows: own rows are always
+            // computed rows, which are never taken from them).
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qc[h][v] = D.qin[v * plane + id];
+        }
         if (ok && cb.mode != MODE_RHS && cb.alpha != 0.0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ub[h][v] = D.base[v * plane + id];
@@ -441,13 +404,13 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     __syncthreads();   // all LDS reads of the staged state are done
 
     // Fluxes back from the face-normal frame to (rho, rho u, rho w, rho E).
-    auto put_x = [&](int cc, int rr, const double* f) {
-        double* e = ex_x + rr * (TX + 1) + cc + 1;
+    auto put_x = [&](int cc, int rr, const FT* f) {
+        FT* e = ex_x + rr * (TX + 1) + cc + 1;
         constexpr int st = TZ * (TX + 1);
         e[0] = f[0]; e[st] = f[1]; e[2 * st] = f[2]; e[3 * st] = f[3];
     };
-    auto put_z = [&](int cc, int rr, const double* f) {
-        double* e = ex_z + (rr + 1) * TX + cc;
+    auto put_z = [&](int cc, int rr, const FT* f) {
+        FT* e = ex_z + (rr + 1) * TX + cc;
         constexpr int st = (TZ + 1) * TX;
         e[0] = f[0]; e[st] = f[2]; e[2 * st] = f[1]; e[3 * st] = f[3];
     };
@@ -457,7 +420,9 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
     if (ex_z4) put_z(ez, re, F[4]);
     __syncthreads();
 
-    // ---- divergence, source and stage combination
+    // ---- divergence (FP64: differences of two face fluxes are exact for FP32
+    // fluxes, so the exchange stays conservative), source and stage
+    // combination.
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const bool ok = h ? ok1 : ok0;
@@ -467,9 +432,21 @@ __device__ void stage_tile(const StageArgs& A, int tile, double* lds)
         double R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double* fx = ex_x + v * TZ * (TX + 1) + r * (TX + 1) + c;
-            const double* fz = ex_z + v * (TZ + 1) * TX + r * TX + c;
-            R[v] = -(fx[1] - fx[0]) * A.inv_dx - (fz[TX] - fz[0]) * D.inv_dz;
+            const FT* fx = ex_x + v * TZ * (TX + 1) + r * (TX + 1) + c;
+            const FT* fz = ex_z + v * (TZ + 1) * TX + r * TX + c;
+            R[v] = -((double)fx[1] - (double)fx[0]) * A.inv_dx -
+                   ((double)fz[TX] - (double)fz[0]) * D.inv_dz;
+        }
+        // Interface viscous flux (FP64, same bits on both sides): it leaves the
+        // lower domain through its top face and enters the upper domain
+        // through its bottom face.
+        if (DOM == 0 && D.gamma_top && row == nz - 1) {
+            R[1] += L.gf[c] * D.inv_dz;
+            R[3] += L.gf[TX + c] * D.inv_dz;
+        }
+        if (DOM == 1 && D.gamma_bot && row == 0) {
+            R[1] -= L.gf[c] * D.inv_dz;
+            R[3] -= L.gf[TX + c] * D.inv_dz;
         }
         R[2] += qc[h][0] * A.gravity;
         R[3] += qc[h][2] * A.gravity;
@@ -533,10 +510,11 @@ __device__ __forceinline__ int xcd_contiguous(int j, int n)
 #define MPRK_WAVES_PER_EU 3
 #endif
 
+template <class FT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
 void stage_kernel(const StageArgs A)
 {
-    __shared__ double lds[LDS_N];
+    __shared__ __align__(16) char smem[lds_bytes<FT>()];
     // Domain A.first takes the first blocks (the host puts the domain with
     // the shorter tiles first so they do not form a tail).
     const int b = blockIdx.x;
@@ -545,8 +523,8 @@ void stage_kernel(const StageArgs A)
     int t = (b < n0) ? b : b - n0;
     // The second domain's blocks keep j % 8 == XCD only if n0 % 8 == 0.
     if (b < n0 || (n0 % 8) == 0) t = xcd_contiguous(t, (b < n0) ? n0 : A.nblocks - n0);
-    if (dom == 0) stage_tile<0>(A, t, lds);
-    else stage_tile<1>(A, t, lds);
+    if (dom == 0) stage_tile<0, FT>(A, t, smem);
+    else stage_tile<1, FT>(A, t, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,10 +576,11 @@ __device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const Tile
 #define MPRK_PERSIST_WAVES_PER_EU 2
 #endif
 
+template <class FT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_PERSIST_WAVES_PER_EU)))
 void persistent_kernel(const PersistArgs P)
 {
-    __shared__ double lds[LDS_N];
+    __shared__ __align__(16) char smem[lds_bytes<FT>()];
     __shared__ int s_go;
     const int G = gridDim.x;
     for (int g = 1; g <= P.gmax; ++g) {
@@ -624,8 +603,8 @@ void persistent_kernel(const PersistArgs P)
                 __syncthreads();
                 if (!s_go) return;
                 const int rel = (tr.tz - D.row_lo / TZ) * D.tiles_x + tr.tx;
-                if (tr.dom == 0) stage_tile<0>(A, rel, lds);
-                else stage_tile<1>(A, rel, lds);
+                if (tr.dom == 0) stage_tile<0, FT>(A, rel, smem);
+                else stage_tile<1, FT>(A, rel, smem);
                 // Every wave's stores are complete before thread 0 publishes.
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                 __syncthreads();
@@ -759,14 +738,16 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_final(const ReduceArgs A)
 hipError_t launch_stage(const StageArgs& a, hipStream_t s)
 {
     if (a.nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stage_kernel, dim3(a.nblocks), dim3(NT), 0, s, a);
+    if (a.flux32) hipLaunchKernelGGL(stage_kernel<float>, dim3(a.nblocks), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL(stage_kernel<double>, dim3(a.nblocks), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const PersistArgs& a, int grid, hipStream_t s)
+hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, hipStream_t s)
 {
     void* args[] = {(void*)&a};
-    return hipLaunchCooperativeKernel((const void*)persistent_kernel, dim3(grid), dim3(NT), args, 0, s);
+    const void* k = flux32 ? (const void*)persistent_kernel<float> : (const void*)persistent_kernel<double>;
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(NT), args, 0, s);
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
@@ -776,11 +757,11 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-int persistent_blocks_per_cu()
+int persistent_blocks_per_cu(bool flux32)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)persistent_kernel, NT, 0) != hipSuccess)
-        return 0;
+    const void* k = flux32 ? (const void*)persistent_kernel<float> : (const void*)persistent_kernel<double>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NT, 0) != hipSuccess) return 0;
     return nb;
 }
 

@@ -54,7 +54,7 @@ def _cfg(**kw):
     ({"prandtl": 0.0}, mprk.EINVAL),
     ({"mu_lower": 0.0}, mprk.EINVAL),
     ({"gravity": float("inf")}, mprk.EINVAL),
-    ({"flux_bits": 32}, mprk.EUNSUPPORTED),
+    ({"flux_bits": 32}, mprk.OK),
     ({"flux_bits": 16}, mprk.EINVAL),
     ({"n_buffer": 2, "strict_buffer": 1}, mprk.EBUFFER),
     ({"n_buffer": 3, "strict_buffer": 1}, mprk.OK),
