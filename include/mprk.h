@@ -66,12 +66,26 @@ enum mprk_status {
                                a completed step)                                      */
 };
 
-/* How mprk_step / mprk_run execute a slow step. */
+/* How mprk_step / mprk_run (and mprk_batch_run) execute a slow step. */
 enum mprk_exec {
     MPRK_EXEC_LAUNCH = 0,     /* one kernel launch per stage (m*s per slow step)        */
-    MPRK_EXEC_PERSISTENT = 1  /* one cooperative launch per run segment: workgroups stay
+    MPRK_EXEC_PERSISTENT = 1, /* one cooperative launch per run segment: workgroups stay
                                  resident and start a tile's next stage as soon as the
                                  tiles it reads have finished the previous one           */
+    MPRK_EXEC_GRAPH = 2       /* the stage launches of one slow step recorded once as a
+                                 HIP graph and replayed per step (rebuilt when dt or the
+                                 tile shape changes)                                     */
+};
+
+/* Tile shapes of the stage kernel (columns x rows of cells per workgroup).
+ * Results do not depend on the shape: every face is evaluated by the same
+ * operations whichever tile holds it. */
+enum mprk_tile {
+    MPRK_TILE_32X16 = 0,      /* default */
+    MPRK_TILE_16X32 = 1,
+    MPRK_TILE_64X8 = 2,
+    MPRK_TILE_32X8 = 3,
+    MPRK_TILE_SHAPES = 4
 };
 
 /* Regions of eq. (semi-discretized-coupled-model), as bits. */
@@ -100,7 +114,9 @@ typedef struct mprk_config {
     double mu_lower;        /* nondimensional viscosity of the lower domain (> 0)    */
     double mu_upper;        /* nondimensional viscosity of the upper domain (> 0)    */
     double gravity;         /* signed vertical gravity; source (0, 0, rho g, rho w g) */
-    int32_t flux_bits;      /* 64: FP64 flux arithmetic (32 is reserved)             */
+    int32_t flux_bits;      /* 64: FP64 throughout; 32: face fluxes in FP32 (state,
+                               stage sums, flux differences and the interface flux
+                               stay FP64, so conservation is unchanged)              */
     int32_t strict_buffer;  /* 1: reject n_buffer < 2s-1 with MPRK_EBUFFER           */
 } mprk_config;
 
@@ -189,6 +205,10 @@ int mprk_set_exec(mprk_ctx* ctx, int mode);
  * neighbour before the run is aborted with MPRK_ETIMEOUT. */
 int mprk_set_wait_limit(mprk_ctx* ctx, double seconds);
 
+/* Tile shape of later launches (an mprk_tile value; default MPRK_TILE_32X16).
+ * Results are bit-identical for every shape. */
+int mprk_set_tile(mprk_ctx* ctx, int shape);
+
 /* Kernel timing aid.  While enabled, every stage launch is bracketed by a
  * pair of HIP events recorded on the context's stream (host-side event
  * objects only; no device allocation).  mprk_profile_take waits for the
@@ -203,6 +223,74 @@ int mprk_destroy(mprk_ctx* ctx);
 
 /* Static description of a status code. */
 const char* mprk_strerror(int code);
+
+/* ---- Batches of independent problems ----------------------------------------
+ * Many coupled two-domain problems ("members": ensembles, served requests),
+ * each with its own sizes, parameters, rate ratio m, base method and step,
+ * advanced together: every launch covers the tiles of all members that have
+ * a stage in it.  A slow step is a fixed number of launches L (the largest
+ * m*s of the batch); member i's stage p (0-based within its slow step) runs
+ * in launch floor(p * L / (m_i s_i)), so every member's stages are spread
+ * evenly over the step and members with small m do not leave launches
+ * empty.  A member's arithmetic is exactly that of a single context with the
+ * same configuration and step: results are bit-identical whatever else is in
+ * the batch, and in every execution mode and tile shape.
+ * All members must share flux_bits.  States are caller-owned device arrays
+ * (layout as above) that must not overlap. */
+typedef struct mprk_member {
+    mprk_config cfg;
+    double* q_lower;        /* device state, updated in place                     */
+    double* q_upper;
+    double dt;              /* slow step of this member (> 0)                      */
+} mprk_member;
+
+typedef struct mprk_batch mprk_batch;
+
+/* Host-only check of every member (as mprk_validate) and of the batch rules
+ * (1..4096 members, one flux_bits, dt > 0).  msg as in mprk_validate. */
+int mprk_batch_validate(const mprk_member* members, int32_t n, char* msg, size_t len);
+
+/* Device workspace bytes of a batch (0 if invalid): the members' scratch
+ * plus the launch tables.  Host-only. */
+size_t mprk_batch_workspace_bytes(const mprk_member* members, int32_t n);
+
+/* Create a batch over caller-owned states and workspace (256-byte aligned,
+ * at least mprk_batch_workspace_bytes).  The member array is copied; the
+ * states must stay valid while the batch lives.  MPRK_EINVAL if states
+ * overlap. */
+int mprk_batch_create(const mprk_member* members, int32_t n, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, mprk_batch** out);
+
+/* Execution mode (mprk_exec) and tile shape (mprk_tile) of later runs. */
+int mprk_batch_set_exec(mprk_batch* batch, int mode);
+int mprk_batch_set_tile(mprk_batch* batch, int shape);
+int mprk_batch_set_wait_limit(mprk_batch* batch, double seconds);
+
+/* Change member's slow step (e.g. after mprk_batch_diagnostics and
+ * mprk_stable_dt); takes effect at the next run. */
+int mprk_batch_set_dt(mprk_batch* batch, int32_t member, double dt);
+
+/* Tile-shape autotuner.  For each shape, times reps repetitions (after one
+ * warm-up) of a slow step's launches with every stage replaced by an RHS
+ * evaluation of the same tiles into the stage scratch (the states are not
+ * modified), with HIP events on the batch's stream; selects the fastest
+ * shape for later runs.  ms_out (optional, MPRK_TILE_SHAPES entries) receives
+ * milliseconds per slow step, *best (optional) the chosen shape.
+ * Synchronises the stream. */
+int mprk_batch_tune(mprk_batch* batch, int32_t reps, double* ms_out, int32_t* best);
+
+/* nsteps slow steps of every member, in place.  Every check_every steps (and
+ * after the last) runs each member's reductions and synchronises; out (n
+ * entries, optional) receives per-member stats of the last check.  Returns
+ * MPRK_ENONFINITE if any member's state is bad (the others still advance
+ * to the check point). */
+int mprk_batch_run(mprk_batch* batch, int64_t nsteps, int64_t check_every, mprk_stats* out);
+
+/* Per-member reductions on the current states (n entries); synchronises. */
+int mprk_batch_diagnostics(mprk_batch* batch, mprk_stats* out);
+
+/* Release the batch (not the caller's memory).  Synchronises its stream. */
+int mprk_batch_destroy(mprk_batch* batch);
 
 #ifdef __cplusplus
 }

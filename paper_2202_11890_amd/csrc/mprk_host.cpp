@@ -1,6 +1,8 @@
 // mprk_host.cpp -- host side of the MPRK library: configuration checks,
 // workspace layout, the stage schedule of one slow step (Algorithm 1 in a
-// low-storage substep form) and the device reductions.
+// low-storage substep form), execution modes (one launch per stage, a graph
+// per slow step, one persistent launch per run segment), batches of
+// independent members, the tile-shape autotuner and the device reductions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,7 +46,25 @@ int shu_osher(int base, double* alpha)
     return -1;
 }
 
-struct Layout {
+int tiles_of(int n, int t) { return (n + t - 1) / t; }
+
+// Fixed tiles of both domains for a tile shape.
+int member_tiles(const mprk_config& c, int shape)
+{
+    const TileDims d = tile_dims(shape);
+    return tiles_of(c.nx, d.tx) * (tiles_of(c.nz_lower, d.tz) + tiles_of(c.nz_upper, d.tz));
+}
+
+int max_member_tiles(const mprk_config& c)
+{
+    int n = 0;
+    for (int sh = 0; sh < TILE_SHAPES; ++sh) n = std::max(n, member_tiles(c, sh));
+    return n;
+}
+
+// Per-member device scratch: stage arrays, retained slow rows, the buffer
+// accumulator and the reduction partials.
+struct CoreLayout {
     int s;
     size_t n_lo, n_up;        // doubles per state array
     size_t off_stage_lo[3];   // stage arrays Q_2..Q_s of each domain
@@ -52,15 +72,10 @@ struct Layout {
     size_t off_ret[3];        // retained slow rows per base stage
     size_t off_acc;
     size_t off_partial, off_final;
-    size_t off_ptab;          // persistent execution: stage table
-    size_t off_ptiles;        //   tile table
-    size_t off_pmember;       //   member record
-    size_t off_pdone;         //   progress counters, then the abort flag
-    int ntiles;               // fixed tiles of both domains
     size_t total;
 };
 
-bool layout_of(const mprk_config* c, Layout* L)
+bool core_layout(const mprk_config* c, CoreLayout* L)
 {
     double al[3];
     int s = shu_osher(c->base_rk, al);
@@ -87,54 +102,854 @@ bool layout_of(const mprk_config* c, Layout* L)
     off += round_up((size_t)2 * RED_BLOCKS * RED_FIELDS * sizeof(double));
     L->off_final = off;
     off += round_up((size_t)2 * RED_FIELDS * sizeof(double));
-    const int tiles_x = (c->nx + TX - 1) / TX;
-    L->ntiles = tiles_x * ((c->nz_lower + TZ - 1) / TZ + (c->nz_upper + TZ - 1) / TZ);
+    L->total = off;
+    return true;
+}
+
+// A context's tables after its core scratch: persistent execution (stage
+// records, tile list, member record, progress counters + abort flag).
+struct CtxLayout {
+    CoreLayout core;
+    size_t off_ptab, off_ptiles, off_pmember, off_pdone;
+    int max_tiles;
+    size_t total;
+};
+
+bool ctx_layout(const mprk_config* c, CtxLayout* L)
+{
+    if (!core_layout(c, &L->core)) return false;
+    size_t off = L->core.total;
+    L->max_tiles = max_member_tiles(*c);
     L->off_ptab = off;
-    off += round_up((size_t)c->m * s * sizeof(StageArgs));
+    off += round_up((size_t)c->m * L->core.s * sizeof(StageArgs));
     L->off_ptiles = off;
-    off += round_up((size_t)L->ntiles * sizeof(TileRef));
+    off += round_up((size_t)L->max_tiles * sizeof(TileRef));
     L->off_pmember = off;
     off += round_up(sizeof(MemberRun));
     L->off_pdone = off;
-    off += round_up((size_t)(L->ntiles + 1) * sizeof(int32_t));
+    off += round_up((size_t)(L->max_tiles + 1) * sizeof(int32_t));
     L->total = off;
     return true;
+}
+
+// One coupled two-domain problem bound to its state and scratch: what the
+// stage schedule needs.
+struct Member {
+    mprk_config cfg;
+    CoreLayout lay;
+    double* q[2];           // lower, upper (caller-owned device memory)
+    char* ws;               // this member's scratch (device)
+    double alpha[3];
+    int fast, slow;         // domain indices
+    int b_lo, b_hi, ret_lo; // buffer rows and retained rows of the slow domain
+
+    void init(const mprk_config& g, const CoreLayout& L, double* ql, double* qu, char* w)
+    {
+        cfg = g;
+        lay = L;
+        q[0] = ql;
+        q[1] = qu;
+        ws = w;
+        shu_osher(g.base_rk, alpha);
+        fast = g.fast_is_lower ? 0 : 1;
+        slow = 1 - fast;
+        const int nzs = g.fast_is_lower ? g.nz_upper : g.nz_lower;
+        if (g.fast_is_lower) {
+            b_lo = 0;
+            b_hi = g.n_buffer;
+            ret_lo = g.n_buffer;
+        } else {
+            b_lo = nzs - g.n_buffer;
+            b_hi = nzs;
+            ret_lo = b_lo - 2;
+        }
+    }
+    double* stage(int dom, int j) const   // Q_{j+1}, j = 1..s-1
+    {
+        return (double*)(ws + (dom == 0 ? lay.off_stage_lo[j - 1] : lay.off_stage_up[j - 1]));
+    }
+    double* ret(int j) const { return (double*)(ws + lay.off_ret[j]); }
+    double* acc() const { return (double*)(ws + lay.off_acc); }
+    int ms() const { return cfg.m * lay.s; }
+};
+
+// Shared per-launch constants; domain-specific fields are filled by callers.
+StageArgs base_args(const Member& mb)
+{
+    const mprk_config& g = mb.cfg;
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.nx = g.nx;
+    a.dx = g.dx;
+    a.inv_dx = 1.0 / g.dx;
+    a.gamma = g.gamma;
+    a.gm1 = g.gamma - 1.0;
+    a.gravity = g.gravity;
+    const double mu1 = g.mu_lower, mu2 = g.mu_upper;
+    const double k1 = mu1 / ((g.gamma - 1.0) * g.prandtl);
+    const double k2 = mu2 / ((g.gamma - 1.0) * g.prandtl);
+    const double dz1 = g.dz_lower, dz2 = g.dz_upper;
+    a.bu = 2.0 * mu1 * mu2 / (dz2 * mu1 + dz1 * mu2);
+    a.bT = 2.0 * k1 * k2 / (dz2 * k1 + dz1 * k2);
+    a.half_dz1_mu1 = dz1 / (2.0 * mu1);
+    a.inv_m = 1.0 / g.m;
+    a.flux32 = g.flux_bits == 32 ? 1 : 0;
+    for (int d = 0; d < 2; ++d) {
+        DomainArgs& D = a.d[d];
+        D.nz = d == 0 ? g.nz_lower : g.nz_upper;
+        D.dz = d == 0 ? dz1 : dz2;
+        D.inv_dz = 1.0 / D.dz;
+        D.mu = d == 0 ? mu1 : mu2;
+        D.kappa = d == 0 ? k1 : k2;
+        D.gamma_top = d == 0;
+        D.gamma_bot = d == 1;
+        D.b_lo = D.b_hi = 0;
+        D.ret_lo = 0;
+    }
+    return a;
+}
+
+void set_rows(DomainArgs& D, int nx, int lo, int hi, int shape)
+{
+    const TileDims t = tile_dims(shape);
+    D.row_lo = lo;
+    D.row_hi = hi;
+    D.tiles_x = tiles_of(nx, t.tx);
+    D.tiles_z = hi > lo ? (hi - 1) / t.tz - lo / t.tz + 1 : 0;   // fixed tiles meeting [lo, hi)
+    D.ntiles = D.tiles_x * D.tiles_z;
+}
+
+// Block count and block order of a stage record: launches that cover only
+// the buffer band of the slow domain put its (short) tiles first, so they run
+// in the first wave of workgroups.
+void finish_record(const Member& mb, StageArgs& a)
+{
+    a.nblocks = a.d[0].ntiles + a.d[1].ntiles;
+    a.first = a.d[mb.slow].use_ret ? mb.slow : 0;
+}
+
+Combine combine(double alpha, double h, int mode)
+{
+    Combine cb;
+    cb.alpha = alpha;
+    cb.beta = 1.0 - alpha;
+    cb.bh = (1.0 - alpha) * h;
+    cb.mode = mode;
+    cb.pad = 0;
+    return cb;
+}
+
+// Launch parameters of global stage (k, j) of a slow step of size dt
+// (Algorithm 1 in the low-storage substep form).
+StageArgs stage_args(const Member& mb, double dt, int k, int j, int shape)
+{
+    const mprk_config& g = mb.cfg;
+    const int s = mb.lay.s, m = g.m;
+    const int F = mb.fast, S = mb.slow;
+    double* qF = mb.q[F];
+    double* qS = mb.q[S];
+    const int nzF = F == 0 ? g.nz_lower : g.nz_upper;
+    const int nzS = S == 0 ? g.nz_lower : g.nz_upper;
+    const double hF = dt / m;
+    StageArgs a = base_args(mb);
+    const double al = mb.alpha[j - 1];
+    const bool last = (j == s);
+
+    // Fast domain: m substeps of dt/m of the base method.
+    DomainArgs& DF = a.d[F];
+    DF.qin = (j == 1) ? qF : mb.stage(F, j - 1);
+    DF.base = qF;
+    DF.out = last ? qF : mb.stage(F, j);
+    DF.main = combine(al, hF, MODE_STAGE);
+    DF.buf = DF.main;
+    set_rows(DF, g.nx, 0, nzF, shape);
+
+    // Slow domain.
+    DomainArgs& DS = a.d[S];
+    DS.qin = (j == 1) ? qS : mb.stage(S, j - 1);
+    DS.base = qS;
+    DS.out = last ? qS : mb.stage(S, j);
+    if (m == 1) {
+        // Single rate: buffer and slow rows are the same base step.
+        DS.main = combine(al, dt, MODE_STAGE);
+        DS.buf = DS.main;
+        set_rows(DS, g.nx, 0, nzS, shape);
+    } else {
+        DS.b_lo = mb.b_lo;
+        DS.b_hi = mb.b_hi;
+        DS.ret_lo = mb.ret_lo;
+        DS.acc = mb.acc();
+        // Buffer: each substep restarts from q^B_n with the full step; the
+        // results of the m trial steps are averaged.
+        int bmode = MODE_STAGE;
+        if (last) bmode = (k == 1) ? MODE_ACC_FIRST : (k < m ? MODE_ACC_ADD : MODE_ACC_FINAL);
+        DS.buf = combine(al, dt, bmode);
+        DS.main = combine(al, dt, MODE_STAGE);
+        if (k == 1) {
+            // Slow rows: one base step; keep the two rows next to the buffer of
+            // each stage value for the later substeps.
+            DS.ret_out = mb.ret(j - 1);
+            set_rows(DS, g.nx, 0, nzS, shape);
+        } else {
+            DS.use_ret = 1;
+            DS.ret_in = mb.ret(j - 1);
+            set_rows(DS, g.nx, mb.b_lo, mb.b_hi, shape);
+        }
+    }
+    finish_record(mb, a);
+    return a;
+}
+
+// The same rows and tiles as stage (k, j) but writing R(state) into the
+// stage scratch and leaving the state alone: the workload the autotuner
+// times.
+StageArgs proxy_args(const Member& mb, double dt, int k, int j, int shape)
+{
+    StageArgs a = stage_args(mb, dt, k, j, shape);
+    for (int d = 0; d < 2; ++d) {
+        DomainArgs& D = a.d[d];
+        D.qin = mb.q[d];
+        D.base = mb.q[d];
+        D.out = mb.stage(d, 1);
+        D.acc = nullptr;
+        D.ret_in = nullptr;
+        D.ret_out = nullptr;
+        D.use_ret = 0;
+        D.main = combine(0.0, 0.0, MODE_RHS);
+        D.buf = D.main;
+    }
+    finish_record(mb, a);
+    return a;
+}
+
+// Device reductions of one member: totals, stability measures, status.
+int member_reduce_launch(const Member& mb, hipStream_t stream, double* host_final)
+{
+    const mprk_config& g = mb.cfg;
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.q[0] = mb.q[0];
+    r.q[1] = mb.q[1];
+    r.nz[0] = g.nz_lower;
+    r.nz[1] = g.nz_upper;
+    r.nx = g.nx;
+    r.inv_dx = 1.0 / g.dx;
+    r.inv_dz[0] = 1.0 / g.dz_lower;
+    r.inv_dz[1] = 1.0 / g.dz_upper;
+    const double coef = std::max(4.0 / 3.0, g.gamma / g.prandtl);
+    r.visc_coef[0] = coef * g.mu_lower * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_lower * g.dz_lower));
+    r.visc_coef[1] = coef * g.mu_upper * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_upper * g.dz_upper));
+    r.gamma = g.gamma;
+    r.gm1 = g.gamma - 1.0;
+    r.partial = (double*)(mb.ws + mb.lay.off_partial);
+    r.final_ = (double*)(mb.ws + mb.lay.off_final);
+    if (launch_reduce(r, stream) != hipSuccess) return MPRK_EHIP;
+    if (hipMemcpyAsync(host_final, r.final_, 2 * RED_FIELDS * sizeof(double), hipMemcpyDeviceToHost,
+                       stream) != hipSuccess)
+        return MPRK_EHIP;
+    return MPRK_OK;
+}
+
+// Stats from the reduced fields (after the stream is synchronised).
+int member_stats(const Member& mb, const double* host_final, int64_t steps, mprk_stats* out)
+{
+    const mprk_config& g = mb.cfg;
+    mprk_stats st;
+    std::memset(&st, 0, sizeof st);
+    const double area[2] = {g.dx * g.dz_lower, g.dx * g.dz_upper};
+    int bad = 0;
+    for (int d = 0; d < 2; ++d) {
+        const double* f = host_final + d * RED_FIELDS;
+        double* tot = d == 0 ? st.totals_lower : st.totals_upper;
+        for (int v = 0; v < NV; ++v) tot[v] = (f[v] + f[NV + v]) * area[d];
+        (d == 0 ? st.lambda_lower : st.lambda_upper) = f[8];
+        (d == 0 ? st.courant_lower : st.courant_upper) = f[9];
+        (d == 0 ? st.visc_lower : st.visc_upper) = f[10];
+        if (f[11] != 0.0) bad = 1;
+    }
+    st.steps_done = steps;
+    st.status = bad;
+    if (out) *out = st;
+    return bad ? MPRK_ENONFINITE : MPRK_OK;
+}
+
+// Device properties needed by the persistent mode.
+int persistent_setup(bool flux32, int shape, int ntiles, double wait_seconds, int* grid,
+                     int64_t* wait_ticks)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MPRK_EHIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MPRK_EHIP;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+        return MPRK_EUNSUPPORTED;
+    const int per_cu = persistent_blocks_per_cu(flux32, shape);
+    if (per_cu <= 0) return MPRK_EHIP;
+    int gsz = per_cu * prop.multiProcessorCount;
+    if (gsz > ntiles) gsz = ntiles;
+    *grid = gsz;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    *wait_ticks = (int64_t)((double)rate_khz * 1000.0 * wait_seconds);
+    return MPRK_OK;
+}
+
+// Tile list and member record of one member for persistent execution.
+void persistent_member(const Member& mb, int member, int shape, int done_base,
+                       std::vector<TileRef>& tiles, MemberRun& mr)
+{
+    const TileDims t = tile_dims(shape);
+    const mprk_config& g = mb.cfg;
+    const int tx = tiles_of(g.nx, t.tx);
+    const int tz[2] = {tiles_of(g.nz_lower, t.tz), tiles_of(g.nz_upper, t.tz)};
+    for (int d = 0; d < 2; ++d)
+        for (int z = 0; z < tz[d]; ++z)
+            for (int x = 0; x < tx; ++x) tiles.push_back(TileRef{member, d, x, z});
+    std::memset(&mr, 0, sizeof mr);
+    mr.tiles_x = tx;
+    mr.tiles_z[0] = tz[0];
+    mr.tiles_z[1] = tz[1];
+    mr.done_base[0] = done_base;
+    mr.done_base[1] = done_base + tx * tz[0];
+}
+
+// A graph of kernel nodes executed in order (one slow step).
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    bool begin()
+    {
+        reset();
+        return hipGraphCreate(&graph, 0) == hipSuccess;
+    }
+    // Appends a kernel node after the previous one.
+    bool add(const KernelRef& k, int blocks, void** args, hipGraphNode_t* prev)
+    {
+        hipKernelNodeParams p;
+        std::memset(&p, 0, sizeof p);
+        p.func = (void*)k.func;
+        p.gridDim = dim3(blocks);
+        p.blockDim = dim3(k.block);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        if (hipGraphAddKernelNode(&node, graph, *prev ? prev : nullptr, *prev ? 1 : 0, &p) != hipSuccess)
+            return false;
+        *prev = node;
+        return true;
+    }
+    bool finish() { return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess; }
+};
+
+bool valid_mode(int mode)
+{
+    return mode == MPRK_EXEC_LAUNCH || mode == MPRK_EXEC_PERSISTENT || mode == MPRK_EXEC_GRAPH;
 }
 
 }  // namespace
 
 struct mprk_ctx {
-    mprk_config cfg;
-    Layout lay;
-    double* q[2];           // lower, upper (caller-owned device memory)
-    char* ws;               // workspace base (device)
+    CtxLayout lay;
+    Member mb;
     hipStream_t stream;
-    double alpha[3];
-    int fast, slow;         // domain indices
-    int b_lo, b_hi, ret_lo; // buffer rows and retained rows of the slow domain
-    int64_t steps;
+    int64_t steps = 0;
     double host_final[2 * RED_FIELDS];
     int exec = MPRK_EXEC_LAUNCH;
+    int shape = TILE_32x16;
+    // persistent execution
     double ptab_dt = 0.0;                     // dt of the uploaded stage table (0: none)
-    bool ptiles_ready = false;
-    int pgrid = 0;                            // persistent grid size
+    int ptab_shape = -1;
+    int ptiles_shape = -1;
+    int pgrid = 0;                            // persistent grid size (0: recompute)
     int64_t wait_ticks = 0;
     double wait_seconds = 2.0;
-    // Host copies of the persistent tables (the asynchronous uploads read them).
-    std::vector<StageArgs> h_tab;
+    std::vector<StageArgs> h_tab;             // host copies read by the async uploads
     std::vector<TileRef> h_tiles;
     MemberRun h_mr;
+    // graph execution: one slow step
+    StepGraph graph;
+    std::vector<StageArgs> g_args;            // argument blocks the graph nodes point to
+    std::vector<void*> g_ptrs;
+    double graph_dt = 0.0;
+    int graph_shape = -1;
+    // kernel timing
     bool prof_on = false;
     size_t prof_used = 0;                     // event pairs recorded since the last take
     std::vector<hipEvent_t> prof_ev;          // start/stop pairs, reused
-
-    double* stage(int dom, int j)   // Q_{j+1}, j = 1..s-1 (0-based j-1)
-    {
-        return (double*)(ws + (dom == 0 ? lay.off_stage_lo[j - 1] : lay.off_stage_up[j - 1]));
-    }
-    double* ret(int j) { return (double*)(ws + lay.off_ret[j]); }
-    double* acc() { return (double*)(ws + lay.off_acc); }
 };
+
+struct mprk_batch {
+    int n = 0;
+    std::vector<Member> mb;
+    std::vector<double> dt;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    bool flux32 = false;
+    int exec = MPRK_EXEC_LAUNCH;
+    int shape = TILE_32x16;
+    int64_t steps = 0;
+    int nslots = 0;                           // launches per slow step (max m*s)
+    int total_ms = 0;                         // stage records per slow step, all members
+    std::vector<int> rec0;                    // first stage record of each member
+    std::vector<int> slot_stage;              // [member][slot]: stage record or -1
+    // device tables (offsets into ws)
+    size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    int max_tiles = 0;
+    // host tables for the current shape
+    int tab_shape = -1;
+    std::vector<StageArgs> h_tab, h_proxy;
+    std::vector<BatchEntry> h_ent;            // [slot][member] (first count entries used)
+    std::vector<int> slot_count, slot_blocks;
+    std::vector<TileRef> h_tiles;
+    std::vector<MemberRun> h_mr;
+    std::vector<int32_t> h_slots;
+    int pgrid = 0, pgrid_shape = -1;
+    int64_t wait_ticks = 0;
+    double wait_seconds = 2.0;
+    StepGraph graph;
+    int graph_shape = -1;
+    std::vector<std::vector<void*>> g_args;   // per node: pointers to its argument values
+    struct NodeArgs { const StageArgs* tab; const BatchEntry* ent; int nent; int nblocks; };
+    std::vector<NodeArgs> g_vals;
+    std::vector<double> host_final;           // [member][2*RED_FIELDS]
+};
+
+namespace {
+
+// ---- single context ------------------------------------------------------
+
+int launch(mprk_ctx* c, const StageArgs& a)
+{
+    if (!c->prof_on) return launch_stage(a, c->shape, c->stream) == hipSuccess ? MPRK_OK : MPRK_EHIP;
+    if (2 * c->prof_used + 2 > c->prof_ev.size()) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) return MPRK_EHIP;
+            c->prof_ev.push_back(ev);
+        }
+    }
+    hipEvent_t e0 = c->prof_ev[2 * c->prof_used], e1 = c->prof_ev[2 * c->prof_used + 1];
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return MPRK_EHIP;
+    if (launch_stage(a, c->shape, c->stream) != hipSuccess) return MPRK_EHIP;
+    if (hipEventRecord(e1, c->stream) != hipSuccess) return MPRK_EHIP;
+    c->prof_used += 1;
+    return MPRK_OK;
+}
+
+int step_launches(mprk_ctx* c, double dt)
+{
+    const int s = c->mb.lay.s, m = c->mb.cfg.m;
+    for (int k = 1; k <= m; ++k) {
+        for (int j = 1; j <= s; ++j) {
+            int rc = launch(c, stage_args(c->mb, dt, k, j, c->shape));
+            if (rc != MPRK_OK) return rc;
+        }
+    }
+    return MPRK_OK;
+}
+
+// A graph of the m*s stage launches of one slow step (rebuilt when dt or the
+// tile shape changes).
+int ctx_graph(mprk_ctx* c, double dt)
+{
+    if (c->graph.exec && c->graph_dt == dt && c->graph_shape == c->shape) return MPRK_OK;
+    const int s = c->mb.lay.s, m = c->mb.cfg.m, ms = m * s;
+    c->g_args.clear();
+    for (int k = 1; k <= m; ++k)
+        for (int j = 1; j <= s; ++j) c->g_args.push_back(stage_args(c->mb, dt, k, j, c->shape));
+    c->g_ptrs.resize(ms);
+    if (!c->graph.begin()) return MPRK_EHIP;
+    const KernelRef kr = stage_kernel_ref(c->mb.cfg.flux_bits == 32, c->shape);
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < ms; ++i) {
+        if (c->g_args[i].nblocks <= 0) continue;
+        c->g_ptrs[i] = &c->g_args[i];
+        if (!c->graph.add(kr, c->g_args[i].nblocks, &c->g_ptrs[i], &prev)) {
+            c->graph.reset();
+            return MPRK_EHIP;
+        }
+    }
+    if (!c->graph.finish()) {
+        c->graph.reset();
+        return MPRK_EHIP;
+    }
+    c->graph_dt = dt;
+    c->graph_shape = c->shape;
+    return MPRK_OK;
+}
+
+// One persistent launch running nsteps slow steps.
+int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
+{
+    const mprk_config& g = c->mb.cfg;
+    const int ms = c->mb.ms();
+    char* ws = c->mb.ws;
+    const int ntiles = member_tiles(g, c->shape);
+    if (c->pgrid <= 0 || c->ptiles_shape != c->shape) {
+        int rc = persistent_setup(g.flux_bits == 32, c->shape, ntiles, c->wait_seconds, &c->pgrid,
+                                  &c->wait_ticks);
+        if (rc != MPRK_OK) {
+            c->pgrid = 0;
+            return rc;
+        }
+    }
+    if (c->ptiles_shape != c->shape) {
+        c->h_tiles.clear();
+        persistent_member(c->mb, 0, c->shape, 0, c->h_tiles, c->h_mr);
+        if (hipMemcpyAsync(ws + c->lay.off_ptiles, c->h_tiles.data(), c->h_tiles.size() * sizeof(TileRef),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return MPRK_EHIP;
+        c->ptiles_shape = c->shape;
+    }
+    if (c->ptab_dt != dt || c->ptab_shape != c->shape) {
+        std::vector<StageArgs>& tab = c->h_tab;
+        tab.clear();
+        for (int k = 1; k <= g.m; ++k)
+            for (int j = 1; j <= c->mb.lay.s; ++j) tab.push_back(stage_args(c->mb, dt, k, j, c->shape));
+        if (hipMemcpyAsync(ws + c->lay.off_ptab, tab.data(), tab.size() * sizeof(StageArgs),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return MPRK_EHIP;
+        c->ptab_dt = dt;
+        c->ptab_shape = c->shape;
+    }
+    if ((int64_t)nsteps * ms > (int64_t)(1 << 30)) return MPRK_EINVAL;
+    std::vector<TileRef> scratch;
+    MemberRun& mr = c->h_mr;
+    persistent_member(c->mb, 0, c->shape, 0, scratch, mr);
+    mr.stages = (const StageArgs*)(ws + c->lay.off_ptab);
+    mr.slot_stage = nullptr;
+    mr.nslots = ms;
+    mr.nsteps = (int32_t)nsteps;
+    if (hipMemcpyAsync(ws + c->lay.off_pmember, &mr, sizeof mr, hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+        return MPRK_EHIP;
+    int32_t* done = (int32_t*)(ws + c->lay.off_pdone);
+    if (launch_fill_i32(done, 0, ntiles + 1, c->stream) != hipSuccess) return MPRK_EHIP;
+    PersistArgs P;
+    std::memset(&P, 0, sizeof P);
+    P.tiles = (const TileRef*)(ws + c->lay.off_ptiles);
+    P.members = (const MemberRun*)(ws + c->lay.off_pmember);
+    P.done = done;
+    P.abort_flag = done + ntiles;
+    P.ntiles = ntiles;
+    P.gmax = (int32_t)(nsteps * ms);
+    P.wait_ticks = c->wait_ticks;
+    if (launch_persistent(P, c->pgrid, g.flux_bits == 32, c->shape, c->stream) != hipSuccess)
+        return MPRK_EHIP;
+    return MPRK_OK;
+}
+
+int advance(mprk_ctx* c, double dt, int64_t nsteps)
+{
+    if (nsteps <= 0) return MPRK_OK;
+    int rc = MPRK_OK;
+    if (c->exec == MPRK_EXEC_PERSISTENT) {
+        rc = run_persistent(c, dt, nsteps);
+    } else if (c->exec == MPRK_EXEC_GRAPH && !c->prof_on) {
+        rc = ctx_graph(c, dt);
+        for (int64_t n = 0; n < nsteps && rc == MPRK_OK; ++n)
+            if (hipGraphLaunch(c->graph.exec, c->stream) != hipSuccess) rc = MPRK_EHIP;
+    } else {
+        for (int64_t n = 0; n < nsteps && rc == MPRK_OK; ++n) rc = step_launches(c, dt);
+    }
+    if (rc == MPRK_OK) c->steps += nsteps;
+    return rc;
+}
+
+int run_reduce(mprk_ctx* c, mprk_stats* out)
+{
+    int rc = member_reduce_launch(c->mb, c->stream, c->host_final);
+    if (rc != MPRK_OK) return rc;
+    int32_t aborted = 0;
+    if (c->exec == MPRK_EXEC_PERSISTENT && c->ptiles_shape >= 0 &&
+        hipMemcpyAsync(&aborted, (int32_t*)(c->mb.ws + c->lay.off_pdone) + member_tiles(c->mb.cfg, c->shape),
+                       sizeof aborted, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return MPRK_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MPRK_EHIP;
+    if (aborted) return MPRK_ETIMEOUT;
+    return member_stats(c->mb, c->host_final, c->steps, out);
+}
+
+// ---- batches -------------------------------------------------------------
+
+struct BatchLayout {
+    std::vector<size_t> core_off;
+    size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    int nslots, total_ms, max_tiles;
+    size_t total;
+};
+
+int batch_check(const mprk_member* mem, int32_t n, char* msg, size_t len)
+{
+    if (!mem || n < 1 || n > 4096) {
+        set_msg(msg, len, "need 1..4096 members");
+        return MPRK_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) {
+        char m2[160];
+        const int rc = mprk_validate(&mem[i].cfg, m2, sizeof m2);
+        if (rc != MPRK_OK) {
+            set_msg(msg, len, "member %d: %s", i, m2);
+            return rc;
+        }
+        if (mem[i].cfg.flux_bits != mem[0].cfg.flux_bits) {
+            set_msg(msg, len, "member %d: every member must use the same flux_bits", i);
+            return MPRK_EINVAL;
+        }
+        if (!(mem[i].dt > 0) || !std::isfinite(mem[i].dt)) {
+            set_msg(msg, len, "member %d: dt must be positive and finite", i);
+            return MPRK_EINVAL;
+        }
+    }
+    return MPRK_OK;
+}
+
+bool batch_layout(const mprk_member* mem, int32_t n, BatchLayout* L)
+{
+    L->core_off.resize(n);
+    size_t off = 0;
+    int ms_max = 0, total_ms = 0, tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        CoreLayout cl;
+        if (!core_layout(&mem[i].cfg, &cl)) return false;
+        L->core_off[i] = off;
+        off += cl.total;
+        const int ms = mem[i].cfg.m * cl.s;
+        ms_max = std::max(ms_max, ms);
+        total_ms += ms;
+        tiles += max_member_tiles(mem[i].cfg);
+    }
+    L->nslots = ms_max;
+    L->total_ms = total_ms;
+    L->max_tiles = tiles;
+    L->off_tab = off;
+    off += round_up((size_t)total_ms * sizeof(StageArgs));
+    L->off_proxy = off;
+    off += round_up((size_t)total_ms * sizeof(StageArgs));
+    L->off_ent = off;
+    off += round_up((size_t)ms_max * n * sizeof(BatchEntry));
+    L->off_slots = off;
+    off += round_up((size_t)ms_max * n * sizeof(int32_t));
+    L->off_ptiles = off;
+    off += round_up((size_t)tiles * sizeof(TileRef));
+    L->off_pmember = off;
+    off += round_up((size_t)n * sizeof(MemberRun));
+    L->off_pdone = off;
+    off += round_up((size_t)(tiles + 1) * sizeof(int32_t));
+    L->total = off;
+    return true;
+}
+
+// Stage records, slot entries and persistent tiles for the batch's shape.
+// Member i's stage p (0-based within a slow step) runs in slot
+// floor(p * nslots / (m_i s_i)), which spreads each member's stages evenly
+// over the slow step's launches.
+int batch_tables(mprk_batch* b)
+{
+    if (b->tab_shape == b->shape) return MPRK_OK;
+    const int n = b->n, L = b->nslots;
+    b->h_tab.clear();
+    b->h_proxy.clear();
+    b->h_ent.assign((size_t)L * n, BatchEntry{0, 0});
+    b->slot_count.assign(L, 0);
+    b->slot_blocks.assign(L, 0);
+    b->h_slots.assign((size_t)n * L, -1);
+    for (int i = 0; i < n; ++i) {
+        const Member& mb = b->mb[i];
+        const int s = mb.lay.s, ms = mb.ms();
+        for (int k = 1; k <= mb.cfg.m; ++k)
+            for (int j = 1; j <= s; ++j) {
+                b->h_tab.push_back(stage_args(mb, b->dt[i], k, j, b->shape));
+                b->h_proxy.push_back(proxy_args(mb, b->dt[i], k, j, b->shape));
+            }
+        for (int p = 0; p < ms; ++p) {
+            const int slot = (int)((int64_t)p * L / ms);
+            b->h_slots[(size_t)i * L + slot] = b->rec0[i] + p;
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        int blocks = 0, cnt = 0;
+        for (int i = 0; i < n; ++i) {
+            const int r = b->h_slots[(size_t)i * L + l];
+            if (r < 0 || b->h_tab[r].nblocks <= 0) continue;
+            b->h_ent[(size_t)l * n + cnt] = BatchEntry{r, blocks};
+            blocks += b->h_tab[r].nblocks;
+            ++cnt;
+        }
+        b->slot_count[l] = cnt;
+        b->slot_blocks[l] = blocks;
+    }
+    b->h_tiles.clear();
+    b->h_mr.assign(n, MemberRun{});
+    int done = 0;
+    for (int i = 0; i < n; ++i) {
+        persistent_member(b->mb[i], i, b->shape, done, b->h_tiles, b->h_mr[i]);
+        done += member_tiles(b->mb[i].cfg, b->shape);
+        MemberRun& mr = b->h_mr[i];
+        mr.stages = (const StageArgs*)(b->ws + b->off_tab) + b->rec0[i];
+        // Slot table of this member, as indices relative to its own records.
+        mr.slot_stage = (const int32_t*)(b->ws + b->off_slots) + (size_t)i * L;
+        mr.nslots = L;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int l = 0; l < L; ++l) {
+            int32_t& r = b->h_slots[(size_t)i * L + l];
+            if (r >= 0) r -= b->rec0[i];
+        }
+    hipStream_t st = b->stream;
+    if (hipMemcpyAsync(b->ws + b->off_tab, b->h_tab.data(), b->h_tab.size() * sizeof(StageArgs),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->off_proxy, b->h_proxy.data(), b->h_proxy.size() * sizeof(StageArgs),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->off_ent, b->h_ent.data(), b->h_ent.size() * sizeof(BatchEntry),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->off_slots, b->h_slots.data(), b->h_slots.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->off_ptiles, b->h_tiles.data(), b->h_tiles.size() * sizeof(TileRef),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return MPRK_EHIP;
+    b->tab_shape = b->shape;
+    b->graph.reset();           // node arguments point at the tables just rewritten
+    return MPRK_OK;
+}
+
+// The slot launches of one slow step (proxy: the autotuner's workload).
+int batch_step_launches(mprk_batch* b, bool proxy)
+{
+    const StageArgs* tab = (const StageArgs*)(b->ws + (proxy ? b->off_proxy : b->off_tab));
+    const BatchEntry* ent = (const BatchEntry*)(b->ws + b->off_ent);
+    for (int l = 0; l < b->nslots; ++l) {
+        if (b->slot_count[l] == 0) continue;
+        if (launch_batch(tab, ent + (size_t)l * b->n, b->slot_count[l], b->slot_blocks[l], b->flux32, b->shape,
+                         b->stream) != hipSuccess)
+            return MPRK_EHIP;
+    }
+    return MPRK_OK;
+}
+
+int batch_graph(mprk_batch* b)
+{
+    if (b->graph.exec && b->graph_shape == b->shape) return MPRK_OK;
+    const int L = b->nslots;
+    b->g_vals.assign(L, mprk_batch::NodeArgs{});
+    b->g_args.assign(L, std::vector<void*>(4, nullptr));
+    if (!b->graph.begin()) return MPRK_EHIP;
+    const KernelRef kr = batch_kernel_ref(b->flux32, b->shape);
+    hipGraphNode_t prev = nullptr;
+    for (int l = 0; l < L; ++l) {
+        if (b->slot_count[l] == 0) continue;
+        mprk_batch::NodeArgs& v = b->g_vals[l];
+        v.tab = (const StageArgs*)(b->ws + b->off_tab);
+        v.ent = (const BatchEntry*)(b->ws + b->off_ent) + (size_t)l * b->n;
+        v.nent = b->slot_count[l];
+        v.nblocks = b->slot_blocks[l];
+        std::vector<void*>& a = b->g_args[l];
+        a[0] = &v.tab;
+        a[1] = &v.ent;
+        a[2] = &v.nent;
+        a[3] = &v.nblocks;
+        if (!b->graph.add(kr, v.nblocks, a.data(), &prev)) {
+            b->graph.reset();
+            return MPRK_EHIP;
+        }
+    }
+    if (!b->graph.finish()) {
+        b->graph.reset();
+        return MPRK_EHIP;
+    }
+    b->graph_shape = b->shape;
+    return MPRK_OK;
+}
+
+int batch_persistent(mprk_batch* b, int64_t nsteps)
+{
+    int ntiles = 0;
+    for (int i = 0; i < b->n; ++i) ntiles += member_tiles(b->mb[i].cfg, b->shape);
+    if (b->pgrid <= 0 || b->pgrid_shape != b->shape) {
+        int rc = persistent_setup(b->flux32, b->shape, ntiles, b->wait_seconds, &b->pgrid, &b->wait_ticks);
+        if (rc != MPRK_OK) {
+            b->pgrid = 0;
+            return rc;
+        }
+        b->pgrid_shape = b->shape;
+    }
+    if ((int64_t)nsteps * b->nslots > (int64_t)(1 << 30)) return MPRK_EINVAL;
+    for (int i = 0; i < b->n; ++i) b->h_mr[i].nsteps = (int32_t)nsteps;
+    if (hipMemcpyAsync(b->ws + b->off_pmember, b->h_mr.data(), b->h_mr.size() * sizeof(MemberRun),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return MPRK_EHIP;
+    int32_t* done = (int32_t*)(b->ws + b->off_pdone);
+    if (launch_fill_i32(done, 0, ntiles + 1, b->stream) != hipSuccess) return MPRK_EHIP;
+    PersistArgs P;
+    std::memset(&P, 0, sizeof P);
+    P.tiles = (const TileRef*)(b->ws + b->off_ptiles);
+    P.members = (const MemberRun*)(b->ws + b->off_pmember);
+    P.done = done;
+    P.abort_flag = done + ntiles;
+    P.ntiles = ntiles;
+    P.gmax = (int32_t)(nsteps * b->nslots);
+    P.wait_ticks = b->wait_ticks;
+    if (launch_persistent(P, b->pgrid, b->flux32, b->shape, b->stream) != hipSuccess) return MPRK_EHIP;
+    return MPRK_OK;
+}
+
+int batch_advance(mprk_batch* b, int64_t nsteps)
+{
+    if (nsteps <= 0) return MPRK_OK;
+    int rc = batch_tables(b);
+    if (rc != MPRK_OK) return rc;
+    if (b->exec == MPRK_EXEC_PERSISTENT) {
+        rc = batch_persistent(b, nsteps);
+    } else if (b->exec == MPRK_EXEC_GRAPH) {
+        rc = batch_graph(b);
+        for (int64_t k = 0; k < nsteps && rc == MPRK_OK; ++k)
+            if (hipGraphLaunch(b->graph.exec, b->stream) != hipSuccess) rc = MPRK_EHIP;
+    } else {
+        for (int64_t k = 0; k < nsteps && rc == MPRK_OK; ++k) rc = batch_step_launches(b, false);
+    }
+    if (rc == MPRK_OK) b->steps += nsteps;
+    return rc;
+}
+
+int batch_reduce(mprk_batch* b, mprk_stats* out)
+{
+    const int n = b->n;
+    b->host_final.resize((size_t)n * 2 * RED_FIELDS);
+    for (int i = 0; i < n; ++i) {
+        int rc = member_reduce_launch(b->mb[i], b->stream, b->host_final.data() + (size_t)i * 2 * RED_FIELDS);
+        if (rc != MPRK_OK) return rc;
+    }
+    int32_t aborted = 0;
+    if (b->exec == MPRK_EXEC_PERSISTENT && b->tab_shape >= 0) {
+        int ntiles = 0;
+        for (int i = 0; i < n; ++i) ntiles += member_tiles(b->mb[i].cfg, b->shape);
+        if (hipMemcpyAsync(&aborted, (int32_t*)(b->ws + b->off_pdone) + ntiles, sizeof aborted,
+                           hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+            return MPRK_EHIP;
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return MPRK_EHIP;
+    if (aborted) return MPRK_ETIMEOUT;
+    int worst = MPRK_OK;
+    for (int i = 0; i < n; ++i) {
+        const int rc = member_stats(b->mb[i], b->host_final.data() + (size_t)i * 2 * RED_FIELDS, b->steps,
+                                    out ? out + i : nullptr);
+        if (rc != MPRK_OK) worst = rc;
+    }
+    return worst;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -224,8 +1039,8 @@ int mprk_validate(const mprk_config* c, char* msg, size_t len)
 size_t mprk_workspace_bytes(const mprk_config* c)
 {
     if (mprk_validate(c, nullptr, 0) != MPRK_OK) return 0;
-    Layout L;
-    if (!layout_of(c, &L)) return 0;
+    CtxLayout L;
+    if (!ctx_layout(c, &L)) return 0;
     return L.total;
 }
 
@@ -257,32 +1072,15 @@ int mprk_create(const mprk_config* cfg, double* q_lower, double* q_upper, void* 
     if (rc != MPRK_OK) return rc;
     if (!q_lower || !q_upper) return MPRK_EINVAL;
     if (((uintptr_t)q_lower | (uintptr_t)q_upper) % sizeof(double)) return MPRK_EINVAL;
-    Layout L;
-    if (!layout_of(cfg, &L)) return MPRK_EINVAL;
+    CtxLayout L;
+    if (!ctx_layout(cfg, &L)) return MPRK_EINVAL;
     if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN))
         return MPRK_EWORKSPACE;
     mprk_ctx* c = new (std::nothrow) mprk_ctx();
     if (!c) return MPRK_EINVAL;
-    c->cfg = *cfg;
     c->lay = L;
-    c->q[0] = q_lower;
-    c->q[1] = q_upper;
-    c->ws = (char*)workspace;
+    c->mb.init(*cfg, L.core, q_lower, q_upper, (char*)workspace);
     c->stream = (hipStream_t)hip_stream;
-    shu_osher(cfg->base_rk, c->alpha);
-    c->fast = cfg->fast_is_lower ? 0 : 1;
-    c->slow = 1 - c->fast;
-    const int nzs = cfg->fast_is_lower ? cfg->nz_upper : cfg->nz_lower;
-    if (cfg->fast_is_lower) {
-        c->b_lo = 0;
-        c->b_hi = cfg->n_buffer;
-        c->ret_lo = cfg->n_buffer;
-    } else {
-        c->b_lo = nzs - cfg->n_buffer;
-        c->b_hi = nzs;
-        c->ret_lo = c->b_lo - 2;
-    }
-    c->steps = 0;
     *out = c;
     return MPRK_OK;
 }
@@ -298,104 +1096,20 @@ int mprk_destroy(mprk_ctx* c)
 {
     if (!c) return MPRK_EINVAL;
     hipError_t e = hipStreamSynchronize(c->stream);
+    c->graph.reset();
     for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
     delete c;
     return e == hipSuccess ? MPRK_OK : MPRK_EHIP;
 }
-
-}  // extern "C"
-
-namespace {
-
-// Shared per-launch constants; domain-specific fields are filled by callers.
-StageArgs base_args(const mprk_ctx* c)
-{
-    const mprk_config& g = c->cfg;
-    StageArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.nx = g.nx;
-    a.dx = g.dx;
-    a.inv_dx = 1.0 / g.dx;
-    a.gamma = g.gamma;
-    a.gm1 = g.gamma - 1.0;
-    a.gravity = g.gravity;
-    const double mu1 = g.mu_lower, mu2 = g.mu_upper;
-    const double k1 = mu1 / ((g.gamma - 1.0) * g.prandtl);
-    const double k2 = mu2 / ((g.gamma - 1.0) * g.prandtl);
-    const double dz1 = g.dz_lower, dz2 = g.dz_upper;
-    a.bu = 2.0 * mu1 * mu2 / (dz2 * mu1 + dz1 * mu2);
-    a.bT = 2.0 * k1 * k2 / (dz2 * k1 + dz1 * k2);
-    a.half_dz1_mu1 = dz1 / (2.0 * mu1);
-    a.inv_m = 1.0 / g.m;
-    a.flux32 = g.flux_bits == 32 ? 1 : 0;
-    for (int d = 0; d < 2; ++d) {
-        DomainArgs& D = a.d[d];
-        D.nz = d == 0 ? g.nz_lower : g.nz_upper;
-        D.dz = d == 0 ? dz1 : dz2;
-        D.inv_dz = 1.0 / D.dz;
-        D.mu = d == 0 ? mu1 : mu2;
-        D.kappa = d == 0 ? k1 : k2;
-        D.gamma_top = d == 0;
-        D.gamma_bot = d == 1;
-        D.b_lo = D.b_hi = 0;
-        D.ret_lo = 0;
-    }
-    return a;
-}
-
-void set_rows(DomainArgs& D, int nx, int lo, int hi)
-{
-    D.row_lo = lo;
-    D.row_hi = hi;
-    D.tiles_x = (nx + TX - 1) / TX;
-    D.tiles_z = hi > lo ? (hi - 1) / TZ - lo / TZ + 1 : 0;   // fixed tiles meeting [lo, hi)
-    D.ntiles = D.tiles_x * D.tiles_z;
-}
-
-Combine combine(double alpha, double h, int mode)
-{
-    Combine cb;
-    cb.alpha = alpha;
-    cb.beta = 1.0 - alpha;
-    cb.bh = (1.0 - alpha) * h;
-    cb.mode = mode;
-    cb.pad = 0;
-    return cb;
-}
-
-int launch(mprk_ctx* c, StageArgs& a)
-{
-    a.nblocks = a.d[0].ntiles + a.d[1].ntiles;
-    // Launches that cover only the buffer band of the slow domain put its
-    // (short) tiles first, so they run in the first wave of workgroups.
-    a.first = (a.d[c->slow].use_ret) ? c->slow : 0;
-    if (!c->prof_on) return launch_stage(a, c->stream) == hipSuccess ? MPRK_OK : MPRK_EHIP;
-    if (2 * c->prof_used + 2 > c->prof_ev.size()) {
-        for (int i = 0; i < 2; ++i) {
-            hipEvent_t ev;
-            if (hipEventCreate(&ev) != hipSuccess) return MPRK_EHIP;
-            c->prof_ev.push_back(ev);
-        }
-    }
-    hipEvent_t e0 = c->prof_ev[2 * c->prof_used], e1 = c->prof_ev[2 * c->prof_used + 1];
-    if (hipEventRecord(e0, c->stream) != hipSuccess) return MPRK_EHIP;
-    if (launch_stage(a, c->stream) != hipSuccess) return MPRK_EHIP;
-    if (hipEventRecord(e1, c->stream) != hipSuccess) return MPRK_EHIP;
-    c->prof_used += 1;
-    return MPRK_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 int mprk_rhs(mprk_ctx* c, const double* q_lower, const double* q_upper, double* r_lower,
              double* r_upper, int mask)
 {
     if (!c || !q_lower || !q_upper || !r_lower || !r_upper) return MPRK_EINVAL;
     if (mask & ~MPRK_REGION_ALL) return MPRK_EINVAL;
-    const mprk_config& g = c->cfg;
-    StageArgs a = base_args(c);
+    const Member& mb = c->mb;
+    const mprk_config& g = mb.cfg;
+    StageArgs a = base_args(mb);
     const double* qs[2] = {q_lower, q_upper};
     double* rs[2] = {r_lower, r_upper};
     for (int d = 0; d < 2; ++d) {
@@ -406,201 +1120,34 @@ int mprk_rhs(mprk_ctx* c, const double* q_lower, const double* q_upper, double* 
         D.main = combine(0.0, 0.0, MODE_RHS);
         D.buf = D.main;
         int lo = 0, hi = 0;
-        if (d == c->fast) {
+        if (d == mb.fast) {
             if (mask & MPRK_REGION_F) hi = D.nz;
         } else {
             const bool wb = mask & MPRK_REGION_B, ws = mask & MPRK_REGION_S;
             if (wb && ws) { lo = 0; hi = D.nz; }
-            else if (wb) { lo = c->b_lo; hi = c->b_hi; }
+            else if (wb) { lo = mb.b_lo; hi = mb.b_hi; }
             else if (ws) {
-                if (g.fast_is_lower) { lo = c->b_hi; hi = D.nz; }
-                else { lo = 0; hi = c->b_lo; }
+                if (g.fast_is_lower) { lo = mb.b_hi; hi = D.nz; }
+                else { lo = 0; hi = mb.b_lo; }
             }
         }
-        set_rows(D, g.nx, lo, hi);
+        set_rows(D, g.nx, lo, hi, c->shape);
     }
+    finish_record(mb, a);
     return launch(c, a);
 }
 
-}  // extern "C"
-
-namespace {
-
-// Launch parameters of global stage (k, j) of a slow step of size dt
-// (Algorithm 1 in the low-storage substep form).
-StageArgs stage_args(mprk_ctx* c, double dt, int k, int j)
-{
-    const mprk_config& g = c->cfg;
-    const int s = c->lay.s, m = g.m;
-    const int F = c->fast, S = c->slow;
-    double* qF = c->q[F];
-    double* qS = c->q[S];
-    const int nzF = F == 0 ? g.nz_lower : g.nz_upper;
-    const int nzS = S == 0 ? g.nz_lower : g.nz_upper;
-    const double hF = dt / m;
-    StageArgs a = base_args(c);
-    const double al = c->alpha[j - 1];
-    const bool last = (j == s);
-
-    // Fast domain: m substeps of dt/m of the base method.
-    DomainArgs& DF = a.d[F];
-    DF.qin = (j == 1) ? qF : c->stage(F, j - 1);
-    DF.base = qF;
-    DF.out = last ? qF : c->stage(F, j);
-    DF.main = combine(al, hF, MODE_STAGE);
-    DF.buf = DF.main;
-    set_rows(DF, g.nx, 0, nzF);
-
-    // Slow domain.
-    DomainArgs& DS = a.d[S];
-    DS.qin = (j == 1) ? qS : c->stage(S, j - 1);
-    DS.base = qS;
-    DS.out = last ? qS : c->stage(S, j);
-    if (m == 1) {
-        // Single rate: buffer and slow rows are the same base step.
-        DS.main = combine(al, dt, MODE_STAGE);
-        DS.buf = DS.main;
-        set_rows(DS, g.nx, 0, nzS);
-    } else {
-        DS.b_lo = c->b_lo;
-        DS.b_hi = c->b_hi;
-        DS.ret_lo = c->ret_lo;
-        DS.acc = c->acc();
-        // Buffer: each substep restarts from q^B_n with the full step; the
-        // results of the m trial steps are averaged.
-        int bmode = MODE_STAGE;
-        if (last) bmode = (k == 1) ? MODE_ACC_FIRST : (k < m ? MODE_ACC_ADD : MODE_ACC_FINAL);
-        DS.buf = combine(al, dt, bmode);
-        DS.main = combine(al, dt, MODE_STAGE);
-        if (k == 1) {
-            // Slow rows: one base step; keep the two rows next to the buffer of
-            // each stage value for the later substeps.
-            DS.ret_out = c->ret(j - 1);
-            set_rows(DS, g.nx, 0, nzS);
-        } else {
-            DS.use_ret = 1;
-            DS.ret_in = c->ret(j - 1);
-            set_rows(DS, g.nx, c->b_lo, c->b_hi);
-        }
-    }
-    return a;
-}
-
-int step_launches(mprk_ctx* c, double dt)
-{
-    const int s = c->lay.s, m = c->cfg.m;
-    for (int k = 1; k <= m; ++k) {
-        for (int j = 1; j <= s; ++j) {
-            StageArgs a = stage_args(c, dt, k, j);
-            int rc = launch(c, a);
-            if (rc != MPRK_OK) return rc;
-        }
-    }
-    return MPRK_OK;
-}
-
-// One persistent launch running nsteps slow steps.
-int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
-{
-    const mprk_config& g = c->cfg;
-    const int s = c->lay.s, m = g.m, ms = m * s;
-    char* ws = c->ws;
-    if (c->pgrid <= 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return MPRK_EHIP;
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MPRK_EHIP;
-        int coop = 0;
-        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
-            return MPRK_EUNSUPPORTED;
-        const int per_cu = persistent_blocks_per_cu(g.flux_bits == 32);
-        if (per_cu <= 0) return MPRK_EHIP;
-        int grid = per_cu * prop.multiProcessorCount;
-        if (grid > c->lay.ntiles) grid = c->lay.ntiles;
-        c->pgrid = grid;
-        int rate_khz = 0;
-        if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
-            rate_khz <= 0)
-            rate_khz = 100000;
-        c->wait_ticks = (int64_t)((double)rate_khz * 1000.0 * c->wait_seconds);
-    }
-    if (!c->ptiles_ready) {
-        const int tiles_x = (g.nx + TX - 1) / TX;
-        const int tz[2] = {(g.nz_lower + TZ - 1) / TZ, (g.nz_upper + TZ - 1) / TZ};
-        std::vector<TileRef>& tiles = c->h_tiles;
-        tiles.clear();
-        tiles.reserve(c->lay.ntiles);
-        for (int d = 0; d < 2; ++d)
-            for (int z = 0; z < tz[d]; ++z)
-                for (int x = 0; x < tiles_x; ++x) tiles.push_back(TileRef{0, d, x, z});
-        if (hipMemcpyAsync(ws + c->lay.off_ptiles, tiles.data(), tiles.size() * sizeof(TileRef),
-                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
-            return MPRK_EHIP;
-        c->ptiles_ready = true;
-    }
-    if (c->ptab_dt != dt) {
-        std::vector<StageArgs>& tab = c->h_tab;
-        tab.clear();
-        tab.reserve(ms);
-        for (int k = 1; k <= m; ++k)
-            for (int j = 1; j <= s; ++j) tab.push_back(stage_args(c, dt, k, j));
-        if (hipMemcpyAsync(ws + c->lay.off_ptab, tab.data(), tab.size() * sizeof(StageArgs),
-                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
-            return MPRK_EHIP;
-        c->ptab_dt = dt;
-    }
-    if ((int64_t)nsteps * ms > (int64_t)(1 << 30)) return MPRK_EINVAL;
-    const int tiles_x = (g.nx + TX - 1) / TX;
-    MemberRun& mr = c->h_mr;
-    std::memset(&mr, 0, sizeof mr);
-    mr.stages = (const StageArgs*)(ws + c->lay.off_ptab);
-    mr.nstages = (int32_t)(nsteps * ms);
-    mr.ms = ms;
-    mr.tiles_x = tiles_x;
-    mr.tiles_z[0] = (g.nz_lower + TZ - 1) / TZ;
-    mr.tiles_z[1] = (g.nz_upper + TZ - 1) / TZ;
-    mr.done_base[0] = 0;
-    mr.done_base[1] = tiles_x * mr.tiles_z[0];
-    if (hipMemcpyAsync(ws + c->lay.off_pmember, &mr, sizeof mr, hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
-        return MPRK_EHIP;
-    int32_t* done = (int32_t*)(ws + c->lay.off_pdone);
-    if (launch_fill_i32(done, 0, c->lay.ntiles + 1, c->stream) != hipSuccess) return MPRK_EHIP;
-    PersistArgs P;
-    std::memset(&P, 0, sizeof P);
-    P.tiles = (const TileRef*)(ws + c->lay.off_ptiles);
-    P.members = (const MemberRun*)(ws + c->lay.off_pmember);
-    P.done = done;
-    P.abort_flag = done + c->lay.ntiles;
-    P.ntiles = c->lay.ntiles;
-    P.gmax = mr.nstages;
-    P.wait_ticks = c->wait_ticks;
-    if (launch_persistent(P, c->pgrid, g.flux_bits == 32, c->stream) != hipSuccess) return MPRK_EHIP;
-    return MPRK_OK;
-}
-
-int advance(mprk_ctx* c, double dt, int64_t nsteps)
-{
-    if (nsteps <= 0) return MPRK_OK;
-    int rc;
-    if (c->exec == MPRK_EXEC_PERSISTENT) {
-        rc = run_persistent(c, dt, nsteps);
-    } else {
-        rc = MPRK_OK;
-        for (int64_t n = 0; n < nsteps && rc == MPRK_OK; ++n) rc = step_launches(c, dt);
-    }
-    if (rc == MPRK_OK) c->steps += nsteps;
-    return rc;
-}
-
-}  // namespace
-
-extern "C" {
-
 int mprk_set_exec(mprk_ctx* c, int mode)
 {
-    if (!c || (mode != MPRK_EXEC_LAUNCH && mode != MPRK_EXEC_PERSISTENT)) return MPRK_EINVAL;
+    if (!c || !valid_mode(mode)) return MPRK_EINVAL;
     c->exec = mode;
+    return MPRK_OK;
+}
+
+int mprk_set_tile(mprk_ctx* c, int shape)
+{
+    if (!c || shape < 0 || shape >= MPRK_TILE_SHAPES) return MPRK_EINVAL;
+    c->shape = shape;
     return MPRK_OK;
 }
 
@@ -616,56 +1163,6 @@ int mprk_step(mprk_ctx* c, double dt)
 {
     if (!c || !(dt > 0) || !std::isfinite(dt)) return MPRK_EINVAL;
     return advance(c, dt, 1);
-}
-
-static int run_reduce(mprk_ctx* c, mprk_stats* out)
-{
-    const mprk_config& g = c->cfg;
-    ReduceArgs r;
-    std::memset(&r, 0, sizeof r);
-    r.q[0] = c->q[0];
-    r.q[1] = c->q[1];
-    r.nz[0] = g.nz_lower;
-    r.nz[1] = g.nz_upper;
-    r.nx = g.nx;
-    r.inv_dx = 1.0 / g.dx;
-    r.inv_dz[0] = 1.0 / g.dz_lower;
-    r.inv_dz[1] = 1.0 / g.dz_upper;
-    const double coef = std::max(4.0 / 3.0, g.gamma / g.prandtl);
-    r.visc_coef[0] = coef * g.mu_lower * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_lower * g.dz_lower));
-    r.visc_coef[1] = coef * g.mu_upper * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_upper * g.dz_upper));
-    r.gamma = g.gamma;
-    r.gm1 = g.gamma - 1.0;
-    r.partial = (double*)(c->ws + c->lay.off_partial);
-    r.final_ = (double*)(c->ws + c->lay.off_final);
-    if (launch_reduce(r, c->stream) != hipSuccess) return MPRK_EHIP;
-    if (hipMemcpyAsync(c->host_final, r.final_, sizeof c->host_final, hipMemcpyDeviceToHost,
-                       c->stream) != hipSuccess)
-        return MPRK_EHIP;
-    int32_t aborted = 0;
-    if (c->exec == MPRK_EXEC_PERSISTENT &&
-        hipMemcpyAsync(&aborted, (int32_t*)(c->ws + c->lay.off_pdone) + c->lay.ntiles,
-                       sizeof aborted, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-        return MPRK_EHIP;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return MPRK_EHIP;
-    if (aborted) return MPRK_ETIMEOUT;
-    mprk_stats st;
-    std::memset(&st, 0, sizeof st);
-    const double area[2] = {g.dx * g.dz_lower, g.dx * g.dz_upper};
-    int bad = 0;
-    for (int d = 0; d < 2; ++d) {
-        const double* f = c->host_final + d * RED_FIELDS;
-        double* tot = d == 0 ? st.totals_lower : st.totals_upper;
-        for (int v = 0; v < NV; ++v) tot[v] = (f[v] + f[NV + v]) * area[d];
-        (d == 0 ? st.lambda_lower : st.lambda_upper) = f[8];
-        (d == 0 ? st.courant_lower : st.courant_upper) = f[9];
-        (d == 0 ? st.visc_lower : st.visc_upper) = f[10];
-        if (f[11] != 0.0) bad = 1;
-    }
-    st.steps_done = c->steps;
-    st.status = bad;
-    if (out) *out = st;
-    return bad ? MPRK_ENONFINITE : MPRK_OK;
 }
 
 int mprk_profile_enable(mprk_ctx* c, int on)
@@ -717,6 +1214,180 @@ int mprk_run(mprk_ctx* c, double dt, int64_t nsteps, int64_t check_every, mprk_s
         if (rc != MPRK_OK) return rc;
     }
     return MPRK_OK;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+int mprk_batch_validate(const mprk_member* members, int32_t n, char* msg, size_t len)
+{
+    return batch_check(members, n, msg, len);
+}
+
+size_t mprk_batch_workspace_bytes(const mprk_member* members, int32_t n)
+{
+    if (batch_check(members, n, nullptr, 0) != MPRK_OK) return 0;
+    BatchLayout L;
+    if (!batch_layout(members, n, &L)) return 0;
+    return L.total;
+}
+
+int mprk_batch_create(const mprk_member* members, int32_t n, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, mprk_batch** out)
+{
+    if (!out) return MPRK_EINVAL;
+    *out = nullptr;
+    int rc = batch_check(members, n, nullptr, 0);
+    if (rc != MPRK_OK) return rc;
+    // States must be distinct, non-overlapping device arrays.
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int i = 0; i < n; ++i) {
+        const mprk_config& g = members[i].cfg;
+        const double* q[2] = {members[i].q_lower, members[i].q_upper};
+        const size_t len[2] = {(size_t)NV * g.nz_lower * g.nx * 8, (size_t)NV * g.nz_upper * g.nx * 8};
+        for (int d = 0; d < 2; ++d) {
+            if (!q[d] || (uintptr_t)q[d] % sizeof(double)) return MPRK_EINVAL;
+            spans.push_back({(uintptr_t)q[d], (uintptr_t)q[d] + len[d]});
+        }
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return MPRK_EINVAL;
+    BatchLayout L;
+    if (!batch_layout(members, n, &L)) return MPRK_EINVAL;
+    if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN)) return MPRK_EWORKSPACE;
+    mprk_batch* b = new (std::nothrow) mprk_batch();
+    if (!b) return MPRK_EINVAL;
+    b->n = n;
+    b->ws = (char*)workspace;
+    b->stream = (hipStream_t)hip_stream;
+    b->flux32 = members[0].cfg.flux_bits == 32;
+    b->mb.resize(n);
+    b->dt.resize(n);
+    b->rec0.resize(n);
+    int rec = 0;
+    for (int i = 0; i < n; ++i) {
+        CoreLayout cl;
+        core_layout(&members[i].cfg, &cl);
+        b->mb[i].init(members[i].cfg, cl, members[i].q_lower, members[i].q_upper,
+                      b->ws + L.core_off[i]);
+        b->dt[i] = members[i].dt;
+        b->rec0[i] = rec;
+        rec += b->mb[i].ms();
+    }
+    b->nslots = L.nslots;
+    b->total_ms = L.total_ms;
+    b->max_tiles = L.max_tiles;
+    b->off_tab = L.off_tab;
+    b->off_proxy = L.off_proxy;
+    b->off_ent = L.off_ent;
+    b->off_slots = L.off_slots;
+    b->off_ptiles = L.off_ptiles;
+    b->off_pmember = L.off_pmember;
+    b->off_pdone = L.off_pdone;
+    *out = b;
+    return MPRK_OK;
+}
+
+int mprk_batch_set_exec(mprk_batch* b, int mode)
+{
+    if (!b || !valid_mode(mode)) return MPRK_EINVAL;
+    b->exec = mode;
+    return MPRK_OK;
+}
+
+int mprk_batch_set_tile(mprk_batch* b, int shape)
+{
+    if (!b || shape < 0 || shape >= MPRK_TILE_SHAPES) return MPRK_EINVAL;
+    b->shape = shape;
+    return MPRK_OK;
+}
+
+int mprk_batch_set_dt(mprk_batch* b, int32_t member, double dt)
+{
+    if (!b || member < 0 || member >= b->n || !(dt > 0) || !std::isfinite(dt)) return MPRK_EINVAL;
+    if (b->dt[member] != dt) {
+        b->dt[member] = dt;
+        b->tab_shape = -1;      // stage records carry dt: rebuild tables and graph
+        b->graph.reset();
+    }
+    return MPRK_OK;
+}
+
+int mprk_batch_set_wait_limit(mprk_batch* b, double seconds)
+{
+    if (!b || !(seconds >= 0.0) || !(seconds <= 3600.0)) return MPRK_EINVAL;
+    b->wait_seconds = seconds;
+    b->pgrid = 0;
+    return MPRK_OK;
+}
+
+int mprk_batch_tune(mprk_batch* b, int32_t reps, double* ms_out, int32_t* best)
+{
+    if (!b || reps < 1 || reps > 1000) return MPRK_EINVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MPRK_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MPRK_EHIP;
+    }
+    const int keep = b->shape;
+    int rc = MPRK_OK, pick = keep;
+    double best_ms = 0.0;
+    for (int sh = 0; sh < MPRK_TILE_SHAPES && rc == MPRK_OK; ++sh) {
+        b->shape = sh;
+        rc = batch_tables(b);
+        if (rc == MPRK_OK) rc = batch_step_launches(b, true);   // warm-up
+        if (rc == MPRK_OK && hipEventRecord(e0, b->stream) != hipSuccess) rc = MPRK_EHIP;
+        for (int r = 0; r < reps && rc == MPRK_OK; ++r) rc = batch_step_launches(b, true);
+        if (rc == MPRK_OK && hipEventRecord(e1, b->stream) != hipSuccess) rc = MPRK_EHIP;
+        float ms = 0.0f;
+        if (rc == MPRK_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = MPRK_EHIP;
+        if (rc != MPRK_OK) break;
+        const double per = (double)ms / reps;
+        if (ms_out) ms_out[sh] = per;
+        if (sh == 0 || per < best_ms) {
+            best_ms = per;
+            pick = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->shape = rc == MPRK_OK ? pick : keep;
+    if (best) *best = b->shape;
+    return rc;
+}
+
+int mprk_batch_run(mprk_batch* b, int64_t nsteps, int64_t check_every, mprk_stats* out)
+{
+    if (!b || nsteps < 0) return MPRK_EINVAL;
+    if (nsteps == 0) return batch_reduce(b, out);
+    const int64_t chunk = check_every > 0 ? check_every : nsteps;
+    for (int64_t done = 0; done < nsteps;) {
+        const int64_t k = std::min(chunk, nsteps - done);
+        int rc = batch_advance(b, k);
+        if (rc != MPRK_OK) return rc;
+        done += k;
+        rc = batch_reduce(b, out);
+        if (rc != MPRK_OK) return rc;
+    }
+    return MPRK_OK;
+}
+
+int mprk_batch_diagnostics(mprk_batch* b, mprk_stats* out)
+{
+    if (!b) return MPRK_EINVAL;
+    return batch_reduce(b, out);
+}
+
+int mprk_batch_destroy(mprk_batch* b)
+{
+    if (!b) return MPRK_EINVAL;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    b->graph.reset();
+    delete b;
+    return e == hipSuccess ? MPRK_OK : MPRK_EHIP;
 }
 
 }  // extern "C"

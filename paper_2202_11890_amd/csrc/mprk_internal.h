@@ -9,25 +9,32 @@ namespace mprk {
 
 constexpr int NV = 4;          // (rho, rho u, rho w, rho E)
 
-// Stage tile: TX columns x TZ rows of cells per workgroup of NT = TX*TZ/2
-// threads; each thread owns a vertical pair of cells.  The conserved state is
-// staged with a 2-cell halo (reconstruction stencil), primitives with a
-// 1-cell halo.
-#ifndef MPRK_TILE_X
-#define MPRK_TILE_X 32
-#endif
-#ifndef MPRK_TILE_Z
-#define MPRK_TILE_Z 16
-#endif
-constexpr int TX = MPRK_TILE_X;
-constexpr int TZ = MPRK_TILE_Z;
-constexpr int NT = TX * TZ / 2;
-static_assert(TZ % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
-static_assert(NT >= 64 + TX && TZ <= 64, "edge faces use waves 0 and 1");
-constexpr int HX = TX + 4;
-constexpr int HZ = TZ + 4;
-constexpr int PX = TX + 2;
-constexpr int PZ = TZ + 2;
+// Stage tile shapes: TX columns x TZ rows of cells per workgroup of
+// TX*TZ/2 threads; each thread owns a vertical pair of cells.  The conserved
+// state is staged with a 2-cell halo (reconstruction stencil), primitives
+// with a 1-cell halo.  Every kernel is instantiated for each shape; the host
+// picks one per context (default 32 x 16, or the autotuner's choice).
+enum TileShape : int32_t {
+    TILE_32x16 = 0,
+    TILE_16x32 = 1,
+    TILE_64x8 = 2,
+    TILE_32x8 = 3,
+    TILE_SHAPES = 4,
+};
+
+struct TileDims {
+    int tx, tz, nt;
+};
+
+inline TileDims tile_dims(int shape)
+{
+    switch (shape) {
+    case TILE_16x32: return {16, 32, 256};
+    case TILE_64x8: return {64, 8, 256};
+    case TILE_32x8: return {32, 8, 128};
+    default: return {32, 16, 256};
+    }
+}
 
 // What a stage launch writes for a cell.
 enum Mode : int32_t {
@@ -106,13 +113,18 @@ struct ReduceArgs {
 struct TileRef {
     int32_t member;
     int32_t dom;       // 0 lower, 1 upper
-    int32_t tx, tz;    // fixed-tile coordinates (TX x TZ, z aligned at multiples of TZ)
+    int32_t tx, tz;    // fixed-tile coordinates (tiles of the launch's shape, z aligned
+                       // at multiples of the tile height)
 };
 
+// Stage g = 1, 2, ... of a persistent launch is slot (g-1) % nslots of slow
+// step (g-1) / nslots; a member computes its stage record slot_stage[slot]
+// there (slot itself when slot_stage is null; nothing when it is -1).
 struct MemberRun {
-    const StageArgs* stages;   // m*s entries, index (k-1)*s + (j-1)
-    int32_t nstages;           // stages to run in this launch (steps * m * s)
-    int32_t ms;
+    const StageArgs* stages;   // m*s records of one slow step, index (k-1)*s + (j-1)
+    const int32_t* slot_stage; // per slot: record index or -1; null: record = slot
+    int32_t nslots;            // slots per slow step
+    int32_t nsteps;            // slow steps in this launch
     int32_t done_base[2];      // progress-counter index of tile (0, 0) per domain
     int32_t tiles_x;
     int32_t tiles_z[2];
@@ -125,14 +137,33 @@ struct PersistArgs {
     int32_t* done;             // progress counters, zero before the launch
     int32_t* abort_flag;       // set (never cleared by the kernel) if a wait timed out
     int32_t ntiles;
-    int32_t gmax;              // largest nstages
+    int32_t gmax;              // stages of the launch: nslots * nsteps
     int64_t wait_ticks;        // longest a task may wait, in wall-clock ticks
 };
 
-hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, hipStream_t s);
+// Batched launches: the blocks of one launch are split into consecutive
+// ranges, one per entry; an entry names the stage record (of some member)
+// whose tiles its blocks compute.
+struct BatchEntry {
+    int32_t arg;       // index into the stage-record table
+    int32_t begin;     // first block of this entry
+};
+
+// Kernel of a launch, for building graphs: function, block size and the
+// argument block.
+struct KernelRef {
+    const void* func;
+    int block;
+};
+
+hipError_t launch_stage(const StageArgs& a, int shape, hipStream_t s);
+KernelRef stage_kernel_ref(bool flux32, int shape);
+hipError_t launch_batch(const StageArgs* tab, const BatchEntry* ent, int nent, int nblocks, bool flux32,
+                        int shape, hipStream_t s);
+KernelRef batch_kernel_ref(bool flux32, int shape);
+hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int shape, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
-int persistent_blocks_per_cu(bool flux32);
+int persistent_blocks_per_cu(bool flux32, int shape);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 
 }  // namespace mprk

@@ -23,19 +23,33 @@ namespace mprk {
 
 namespace {
 
-constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
-constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
-constexpr int LDS_EX = NV * TZ * (TX + 1) + NV * (TZ + 1) * TX;  // face fluxes
-static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
-constexpr int LOAD_RG = NT / HX;                        // row groups of the loader
-constexpr int LOAD_THREADS = LOAD_RG * HX;
-constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG; // rows per loader thread
+template <int X, int Z>
+struct Shape {
+    static constexpr int TX = X, TZ = Z, NT = X * Z / 2;
+    static constexpr int HX = X + 4, HZ = Z + 4;      // staged state with a 2-cell halo
+    static constexpr int PX = X + 2, PZ = Z + 2;      // primitives with a 1-cell halo
+    static constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
+    static constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
+    static constexpr int LDS_EX = NV * Z * (X + 1) + NV * (Z + 1) * X;  // face fluxes
+    static constexpr int LOAD_RG = NT / HX;           // row groups of the loader
+    static constexpr int LOAD_THREADS = LOAD_RG * HX;
+    static constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG;  // rows per loader thread
+    static_assert(Z % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
+    static_assert(NT >= 64 + X && Z <= 64, "edge faces use waves 0 and 1");
+    static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
+    static_assert(LOAD_RG >= 1, "loader needs a full row of threads");
+    // Shared memory of one tile: the staged state and primitives in the flux
+    // type FT (the flux exchange reuses that space), then the per-column
+    // interface flux in FP64.
+    template <class FT>
+    static constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 2 * X * 8; }
+};
 
-// Shared memory of one tile: the staged state and primitives in the flux
-// type FT (the flux exchange reuses that space), then the per-column
-// interface flux in FP64.
-template <class FT>
-constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 2 * TX * 8; }
+// Brings a shape's constants into a function's scope.
+#define MPRK_SHAPE_CONSTANTS(S)                                                          \
+    constexpr int TX = S::TX, TZ = S::TZ, NT = S::NT, HX = S::HX, HZ = S::HZ;            \
+    constexpr int PX = S::PX, PZ = S::PZ;                                                \
+    (void)TX; (void)TZ; (void)NT; (void)HX; (void)HZ; (void)PX; (void)PZ
 
 __device__ __forceinline__ int wrapx(int c, int nx)
 {
@@ -148,8 +162,10 @@ struct Lds {
     double* gf;   // [2][TX]: interface flux (x-momentum, energy) per column
 };
 
-__device__ __forceinline__ int qidx(int v, int r, int c) { return (v * HZ + r + 2) * HX + c + 2; }
-__device__ __forceinline__ int pidx(int f, int r, int c) { return (f * PZ + r + 1) * PX + c + 1; }
+template <class S>
+__device__ __forceinline__ int qidx(int v, int r, int c) { return (v * S::HZ + r + 2) * S::HX + c + 2; }
+template <class S>
+__device__ __forceinline__ int pidx(int f, int r, int c) { return (f * S::PZ + r + 1) * S::PX + c + 1; }
 
 // Boundary kinds of a face.
 enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
@@ -162,7 +178,7 @@ enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
 //   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; likewise.
 // At walls and at the interface the viscous part is not added here: walls
 // carry none, and the interface flux enters the divergence in FP64.
-template <class FT, int dir>
+template <class FT, int dir, class S>
 __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& D, const Lds<FT>& L,
                                           int c, int r, int kind, FT F[NV])
 {
@@ -171,6 +187,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     // written out, every call site performs the same IEEE operations, so both
     // obtain the same bits and the flux differences telescope exactly.
 #pragma clang fp contract(off)
+    MPRK_SHAPE_CONSTANTS(S);
     const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
     const FT h = FT(0.5), q4 = FT(0.25);
     constexpr int sn = dir ? HX : 1;         // normal stride in the state tile
@@ -182,7 +199,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     // Reconstruction of conserved variables with central cell gradients:
     // qL = q_c + (q_{c+1} - q_{c-1})/4, qR = q_{c+1} - (q_{c+2} - q_c)/4.
     FT qL[NV], qR[NV];
-    const int base = qidx(0, r, c);
+    const int base = qidx<S>(0, r, c);
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const FT* s = L.q + comp[k] * plane + base;
@@ -236,7 +253,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     {
         // Common values: averaged velocity, normal derivative by finite
         // difference, tangential derivative by averaging cell gradients.
-        const int pb = pidx(0, r, c);
+        const int pb = pidx<S>(0, r, c);
         constexpr int pn = dir ? PX : 1;
         constexpr int pt = dir ? 1 : PX;
         constexpr int fn = dir ? 1 : 0;      // normal velocity in the primitive tile
@@ -262,9 +279,12 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     }
 }
 
-template <int DOM, class FT>
-__device__ void stage_tile(const StageArgs& A, int tile, char* smem)
+template <int DOM, class FT, class S>
+__device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* smem)
 {
+    MPRK_SHAPE_CONSTANTS(S);
+    constexpr int LDS_Q = S::LDS_Q, LDS_P = S::LDS_P;
+    constexpr int LOAD_RG = S::LOAD_RG, LOAD_THREADS = S::LOAD_THREADS, LOAD_ROWS = S::LOAD_ROWS;
     const DomainArgs& D = A.d[DOM];
     const DomainArgs& O = A.d[1 - DOM];
     const int tid = threadIdx.x;
@@ -360,7 +380,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, char* smem)
     // ---- primitives on the tile plus a 1-cell ring
     for (int idx = tid; idx < PZ * PX; idx += NT) {
         const int pr = idx / PX, pc = idx - pr * PX;
-        const int b = qidx(0, pr - 1, pc - 1);
+        const int b = qidx<S>(0, pr - 1, pc - 1);
         FT u, w, T;
         primitives<FT>(L.q[b], L.q[b + HZ * HX], L.q[b + 2 * HZ * HX], L.q[b + 3 * HZ * HX],
                        FT(A.gamma), FT(A.gm1), u, w, T);
@@ -383,12 +403,12 @@ __device__ void stage_tile(const StageArgs& A, int tile, char* smem)
     const int kind4 = (z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
     FT F[5][NV];
-    if (ok0) face_flux<FT, 0>(A, D, L, c, r0, FACE_INTERIOR, F[0]);
-    if (ok1) face_flux<FT, 0>(A, D, L, c, r0 + 1, FACE_INTERIOR, F[1]);
-    if (ok0) face_flux<FT, 1>(A, D, L, c, r0, kind2, F[2]);
-    if (ok1) face_flux<FT, 1>(A, D, L, c, r0 + 1, kind3, F[3]);
-    if (ex_x4) face_flux<FT, 0>(A, D, L, -1, tid, FACE_INTERIOR, F[4]);
-    if (ex_z4) face_flux<FT, 1>(A, D, L, ez, re, kind4, F[4]);
+    if (ok0) face_flux<FT, 0, S>(A, D, L, c, r0, FACE_INTERIOR, F[0]);
+    if (ok1) face_flux<FT, 0, S>(A, D, L, c, r0 + 1, FACE_INTERIOR, F[1]);
+    if (ok0) face_flux<FT, 1, S>(A, D, L, c, r0, kind2, F[2]);
+    if (ok1) face_flux<FT, 1, S>(A, D, L, c, r0 + 1, kind3, F[3]);
+    if (ex_x4) face_flux<FT, 0, S>(A, D, L, -1, tid, FACE_INTERIOR, F[4]);
+    if (ex_z4) face_flux<FT, 1, S>(A, D, L, ez, re, kind4, F[4]);
 
     // Pointwise FP64 reads for the combination (the stage value itself when
     // the fluxes are FP32, and the substep base U); they complete while the
@@ -407,7 +427,7 @@ __device__ void stage_tile(const StageArgs& A, int tile, char* smem)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             Ub[h][v] = 0.0;
-            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx(v, r0 + h, c)] : 0.0;
+            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx<S>(v, r0 + h, c)] : 0.0;
         }
         if (ok && sizeof(FT) != 8) {
             // Stage values of this tile's own rows come from the state or the
@@ -530,21 +550,46 @@ __device__ __forceinline__ int xcd_contiguous(int j, int n)
 #define MPRK_WAVES_PER_EU 3
 #endif
 
-template <class FT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
-void stage_kernel(const StageArgs A)
+// Tiles of one stage record, block b of its nblocks: domain A.first takes the
+// first blocks (the host puts the domain with the shorter tiles first so
+// they do not form a tail).
+template <class FT, class S>
+__device__ __forceinline__ void record_block(const StageArgs& A, int b, bool remap, char* smem)
 {
-    __shared__ __align__(16) char smem[lds_bytes<FT>()];
-    // Domain A.first takes the first blocks (the host puts the domain with
-    // the shorter tiles first so they do not form a tail).
-    const int b = blockIdx.x;
     const int n0 = A.d[A.first].ntiles;
     const int dom = (b < n0) ? A.first : 1 - A.first;
     int t = (b < n0) ? b : b - n0;
     // The second domain's blocks keep j % 8 == XCD only if n0 % 8 == 0.
-    if (b < n0 || (n0 % 8) == 0) t = xcd_contiguous(t, (b < n0) ? n0 : A.nblocks - n0);
-    if (dom == 0) stage_tile<0, FT>(A, t, smem);
-    else stage_tile<1, FT>(A, t, smem);
+    if (remap && (b < n0 || (n0 % 8) == 0)) t = xcd_contiguous(t, (b < n0) ? n0 : A.nblocks - n0);
+    if (dom == 0) stage_tile<0, FT, S>(A, t, smem);
+    else stage_tile<1, FT, S>(A, t, smem);
+}
+
+template <class FT, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
+void stage_kernel(const StageArgs A)
+{
+    __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
+    record_block<FT, S>(A, blockIdx.x, true, smem);
+}
+
+// One launch over several stage records (batched members): blocks are
+// remapped so that each XCD takes a contiguous range, then located in the
+// entry table (a uniform binary search over the entries' first blocks).
+template <class FT, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
+void batch_kernel(const StageArgs* __restrict__ tab, const BatchEntry* __restrict__ ent, int nent,
+                  int nblocks)
+{
+    __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
+    const int b = xcd_contiguous(blockIdx.x, nblocks);
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    record_block<FT, S>(tab[ent[lo].arg], b - ent[lo].begin, false, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -596,11 +641,11 @@ __device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const Tile
 #define MPRK_PERSIST_WAVES_PER_EU 2
 #endif
 
-template <class FT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MPRK_PERSIST_WAVES_PER_EU)))
+template <class FT, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(MPRK_PERSIST_WAVES_PER_EU)))
 void persistent_kernel(const PersistArgs P)
 {
-    __shared__ __align__(16) char smem[lds_bytes<FT>()];
+    __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
     __shared__ int s_go;
     const int G = gridDim.x;
     for (int g = 1; g <= P.gmax; ++g) {
@@ -610,11 +655,12 @@ void persistent_kernel(const PersistArgs P)
             const int t = (G % 8 == 0) ? xcd_contiguous(i, P.ntiles) : i;
             const TileRef tr = P.tiles[t];
             const MemberRun& M = P.members[tr.member];
-            if (g > M.nstages) continue;
-            const StageArgs& A = M.stages[(g - 1) % M.ms];
+            const int step = (g - 1) / M.nslots, slot = (g - 1) - step * M.nslots;
+            const int rec = step >= M.nsteps ? -1 : (M.slot_stage ? M.slot_stage[slot] : slot);
+            const StageArgs& A = M.stages[rec < 0 ? 0 : rec];
             const DomainArgs& D = A.d[tr.dom];
-            const int z0 = tr.tz * TZ;
-            const bool work = D.row_hi > D.row_lo && z0 < D.row_hi && z0 + TZ > D.row_lo;
+            const int z0 = tr.tz * S::TZ;
+            const bool work = rec >= 0 && D.row_hi > D.row_lo && z0 < D.row_hi && z0 + S::TZ > D.row_lo;
             if (work) {
                 if (threadIdx.x < 64) {
                     const bool ok = wait_inputs(P, M, tr, g);
@@ -622,9 +668,9 @@ void persistent_kernel(const PersistArgs P)
                 }
                 __syncthreads();
                 if (!s_go) return;
-                const int rel = (tr.tz - D.row_lo / TZ) * D.tiles_x + tr.tx;
-                if (tr.dom == 0) stage_tile<0, FT>(A, rel, smem);
-                else stage_tile<1, FT>(A, rel, smem);
+                const int rel = (tr.tz - D.row_lo / S::TZ) * D.tiles_x + tr.tx;
+                if (tr.dom == 0) stage_tile<0, FT, S>(A, rel, smem);
+                else stage_tile<1, FT, S>(A, rel, smem);
                 // Every wave's stores are complete before thread 0 publishes.
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                 __syncthreads();
@@ -753,21 +799,76 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_final(const ReduceArgs A)
     if (threadIdx.x == 0) red_store(A.final_ + (size_t)dom * RED_FIELDS, m);
 }
 
-}  // namespace
+using S0 = Shape<32, 16>;
+using S1 = Shape<16, 32>;
+using S2 = Shape<64, 8>;
+using S3 = Shape<32, 8>;
 
-hipError_t launch_stage(const StageArgs& a, hipStream_t s)
+// Calls f.template operator()<FT, S>() for the flux type and shape.
+template <class F>
+auto with_kernel(bool flux32, int shape, F&& f)
 {
-    if (a.nblocks <= 0) return hipSuccess;
-    if (a.flux32) hipLaunchKernelGGL(stage_kernel<float>, dim3(a.nblocks), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL(stage_kernel<double>, dim3(a.nblocks), dim3(NT), 0, s, a);
-    return hipGetLastError();
+    switch (shape) {
+    case TILE_16x32: return flux32 ? f.template operator()<float, S1>() : f.template operator()<double, S1>();
+    case TILE_64x8: return flux32 ? f.template operator()<float, S2>() : f.template operator()<double, S2>();
+    case TILE_32x8: return flux32 ? f.template operator()<float, S3>() : f.template operator()<double, S3>();
+    default: return flux32 ? f.template operator()<float, S0>() : f.template operator()<double, S0>();
+    }
 }
 
-hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, hipStream_t s)
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, int shape, hipStream_t s)
 {
-    void* args[] = {(void*)&a};
-    const void* k = flux32 ? (const void*)persistent_kernel<float> : (const void*)persistent_kernel<double>;
-    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(NT), args, 0, s);
+    if (a.nblocks <= 0) return hipSuccess;
+    return with_kernel(a.flux32 != 0, shape, [&]<class FT, class S>() {
+        hipLaunchKernelGGL((stage_kernel<FT, S>), dim3(a.nblocks), dim3(S::NT), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+KernelRef stage_kernel_ref(bool flux32, int shape)
+{
+    return with_kernel(flux32, shape, []<class FT, class S>() {
+        return KernelRef{(const void*)stage_kernel<FT, S>, S::NT};
+    });
+}
+
+hipError_t launch_batch(const StageArgs* tab, const BatchEntry* ent, int nent, int nblocks, bool flux32,
+                        int shape, hipStream_t s)
+{
+    if (nblocks <= 0 || nent <= 0) return hipSuccess;
+    return with_kernel(flux32, shape, [&]<class FT, class S>() {
+        hipLaunchKernelGGL((batch_kernel<FT, S>), dim3(nblocks), dim3(S::NT), 0, s, tab, ent, nent, nblocks);
+        return hipGetLastError();
+    });
+}
+
+KernelRef batch_kernel_ref(bool flux32, int shape)
+{
+    return with_kernel(flux32, shape, []<class FT, class S>() {
+        return KernelRef{(const void*)batch_kernel<FT, S>, S::NT};
+    });
+}
+
+hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int shape, hipStream_t s)
+{
+    return with_kernel(flux32, shape, [&]<class FT, class S>() {
+        void* args[] = {(void*)&a};
+        return hipLaunchCooperativeKernel((const void*)persistent_kernel<FT, S>, dim3(grid), dim3(S::NT),
+                                          args, 0, s);
+    });
+}
+
+int persistent_blocks_per_cu(bool flux32, int shape)
+{
+    return with_kernel(flux32, shape, []<class FT, class S>() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)persistent_kernel<FT, S>, S::NT,
+                                                         0) != hipSuccess)
+            return 0;
+        return nb;
+    });
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
@@ -775,14 +876,6 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, value, n);
     return hipGetLastError();
-}
-
-int persistent_blocks_per_cu(bool flux32)
-{
-    int nb = 0;
-    const void* k = flux32 ? (const void*)persistent_kernel<float> : (const void*)persistent_kernel<double>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NT, 0) != hipSuccess) return 0;
-    return nb;
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s)

@@ -78,6 +78,48 @@ def large() -> Workload:
                     nz_upper=512, base=3, m=4, steps=1000, n_buffer=4, seed=1)
 
 
+def ensemble(n: int = 64, seed0: int = 100):
+    """Batched ensemble: n independent two-domain problems of the small and
+    large workloads' setup, member i seeded with seed0 + i: nx uniform in
+    [128, 512], nz uniform in [64, 256] (the same for both domains),
+    perturbation amplitude log-uniform in [1e-3, 1e-1], viscosity log-uniform
+    in [1e-4, 1e-2] (both domains), m uniform in {2, 4, 8}; RK2 base, 4
+    buffer rows, 500 slow steps."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        nx = int(rng.integers(128, 513))
+        nz = int(rng.integers(64, 257))
+        amp = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e-1))))
+        mu = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+        m = int(rng.choice([2, 4, 8]))
+        out.append(Workload("ensemble member %d" % i, nx=nx, nz_lower=nz, nz_upper=nz, base=2, m=m,
+                            steps=500, n_buffer=4, mu_lower=mu, mu_upper=mu, amplitude=amp,
+                            seed=seed0 + i))
+    return out
+
+
+def serving_requests(n: int, rate: float, seed: int = 7):
+    """Serving workload: n requests with Poisson arrivals at `rate` per second
+    (exponential gaps), as (arrival_seconds, Workload): nx log-uniform in
+    [64, 1024] with nz = nx/2 per domain, 50..500 slow steps, m in {2, 4},
+    RK2 base, seeded perturbation."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        nx = int(round(np.exp(rng.uniform(np.log(64), np.log(1024)))))
+        nx = max(64, min(1024, nx))
+        nz = max(8, nx // 2)
+        steps = int(rng.integers(50, 501))
+        m = int(rng.choice([2, 4]))
+        w = Workload("request %d" % i, nx=nx, nz_lower=nz, nz_upper=nz, base=2, m=m, steps=steps,
+                     n_buffer=4, seed=10_000 + seed * 1000 + i)
+        out.append((t, w))
+    return out
+
+
 def centre(w: Workload):
     rng = np.random.default_rng(w.seed)
     xc = rng.uniform(-w.lx / 2, w.lx / 2)

@@ -12,7 +12,9 @@ import os
 
 ABI_VERSION = 1
 OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
-EXEC_LAUNCH, EXEC_PERSISTENT = 0, 1
+EXEC_LAUNCH, EXEC_PERSISTENT, EXEC_GRAPH = 0, 1, 2
+TILE_32X16, TILE_16X32, TILE_64X8, TILE_32X8, TILE_SHAPES = 0, 1, 2, 3, 4
+TILE_NAMES = ("32x16", "16x32", "64x8", "32x8")
 REGION_F, REGION_B, REGION_S, REGION_ALL = 1, 2, 4, 7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -77,10 +79,22 @@ class mprk_stats(ctypes.Structure):
         }
 
 
+class mprk_member(ctypes.Structure):
+    _fields_ = [
+        ("cfg", mprk_config),
+        ("q_lower", ctypes.c_void_p),
+        ("q_upper", ctypes.c_void_p),
+        ("dt", ctypes.c_double),
+    ]
+
+
 EXPORTS = ("mprk_validate", "mprk_workspace_bytes", "mprk_create", "mprk_set_stream", "mprk_rhs",
            "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_stable_dt", "mprk_set_exec",
-           "mprk_set_wait_limit",
-           "mprk_profile_enable", "mprk_profile_take", "mprk_destroy", "mprk_strerror")
+           "mprk_set_wait_limit", "mprk_set_tile",
+           "mprk_profile_enable", "mprk_profile_take", "mprk_destroy", "mprk_strerror",
+           "mprk_batch_validate", "mprk_batch_workspace_bytes", "mprk_batch_create",
+           "mprk_batch_set_exec", "mprk_batch_set_tile", "mprk_batch_set_wait_limit", "mprk_batch_set_dt",
+           "mprk_batch_tune", "mprk_batch_run", "mprk_batch_diagnostics", "mprk_batch_destroy")
 
 _lib = None
 
@@ -115,6 +129,21 @@ def load(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_double)]
     lib.mprk_set_exec.argtypes = [V, ctypes.c_int]
     lib.mprk_set_wait_limit.argtypes = [V, ctypes.c_double]
+    lib.mprk_set_tile.argtypes = [V, ctypes.c_int]
+    M = ctypes.POINTER(mprk_member)
+    lib.mprk_batch_validate.argtypes = [M, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]
+    lib.mprk_batch_workspace_bytes.argtypes = [M, ctypes.c_int32]
+    lib.mprk_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.mprk_batch_create.argtypes = [M, ctypes.c_int32, V, ctypes.c_size_t, V, ctypes.POINTER(V)]
+    lib.mprk_batch_set_exec.argtypes = [V, ctypes.c_int]
+    lib.mprk_batch_set_tile.argtypes = [V, ctypes.c_int]
+    lib.mprk_batch_set_wait_limit.argtypes = [V, ctypes.c_double]
+    lib.mprk_batch_set_dt.argtypes = [V, ctypes.c_int32, ctypes.c_double]
+    lib.mprk_batch_tune.argtypes = [V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.mprk_batch_run.argtypes = [V, ctypes.c_int64, ctypes.c_int64, S]
+    lib.mprk_batch_diagnostics.argtypes = [V, S]
+    lib.mprk_batch_destroy.argtypes = [V]
     lib.mprk_profile_enable.argtypes = [V, ctypes.c_int]
     lib.mprk_profile_take.argtypes = [V, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
@@ -185,6 +214,10 @@ def mprk_set_wait_limit(ctx, seconds):
     return load().mprk_set_wait_limit(ctx, float(seconds))
 
 
+def mprk_set_tile(ctx, shape):
+    return load().mprk_set_tile(ctx, int(shape))
+
+
 def mprk_profile_enable(ctx, on):
     return load().mprk_profile_enable(ctx, int(bool(on)))
 
@@ -198,6 +231,69 @@ def mprk_profile_take(ctx):
 
 def mprk_destroy(ctx):
     return load().mprk_destroy(ctx)
+
+
+def _members(members):
+    arr = (mprk_member * len(members))()
+    for i, m in enumerate(members):
+        arr[i] = m
+    return arr
+
+
+def mprk_batch_validate(members):
+    buf = ctypes.create_string_buffer(256)
+    rc = load().mprk_batch_validate(_members(members), len(members), buf, 256)
+    return rc, buf.value.decode()
+
+
+def mprk_batch_workspace_bytes(members) -> int:
+    return int(load().mprk_batch_workspace_bytes(_members(members), len(members)))
+
+
+def mprk_batch_create(members, ws_ptr, ws_bytes, stream_ptr):
+    out = ctypes.c_void_p()
+    rc = load().mprk_batch_create(_members(members), len(members), ws_ptr, ws_bytes, stream_ptr,
+                                  ctypes.byref(out))
+    return rc, out.value
+
+
+def mprk_batch_set_exec(b, mode):
+    return load().mprk_batch_set_exec(b, int(mode))
+
+
+def mprk_batch_set_tile(b, shape):
+    return load().mprk_batch_set_tile(b, int(shape))
+
+
+def mprk_batch_set_wait_limit(b, seconds):
+    return load().mprk_batch_set_wait_limit(b, float(seconds))
+
+
+def mprk_batch_set_dt(b, member, dt):
+    return load().mprk_batch_set_dt(b, int(member), float(dt))
+
+
+def mprk_batch_tune(b, reps):
+    ms = (ctypes.c_double * TILE_SHAPES)()
+    best = ctypes.c_int32()
+    rc = load().mprk_batch_tune(b, int(reps), ms, ctypes.byref(best))
+    return rc, list(ms), best.value
+
+
+def mprk_batch_run(b, n, nsteps, check_every):
+    st = (mprk_stats * n)()
+    rc = load().mprk_batch_run(b, int(nsteps), int(check_every), st)
+    return rc, list(st)
+
+
+def mprk_batch_diagnostics(b, n):
+    st = (mprk_stats * n)()
+    rc = load().mprk_batch_diagnostics(b, st)
+    return rc, list(st)
+
+
+def mprk_batch_destroy(b):
+    return load().mprk_batch_destroy(b)
 
 
 # ---- convenience ----------------------------------------------------------
@@ -226,7 +322,7 @@ class Solver:
     """Owns the workspace tensor and the context; the state tensors belong to
     the caller and are updated in place."""
 
-    def __init__(self, cfg: mprk_config, q_lower, q_upper, stream=None, exec_mode=None):
+    def __init__(self, cfg: mprk_config, q_lower, q_upper, stream=None, exec_mode=None, tile=None):
         import torch
 
         for t in (q_lower, q_upper):
@@ -250,6 +346,8 @@ class Solver:
         _check(rc, "mprk_create")
         if exec_mode is not None:
             self.set_exec(exec_mode)
+        if tile is not None:
+            self.set_tile(tile)
 
     def rhs(self, q_lower, q_upper, r_lower, r_upper, mask=REGION_ALL):
         _check(mprk_rhs(self.ctx, q_lower.data_ptr(), q_upper.data_ptr(), r_lower.data_ptr(),
@@ -282,6 +380,9 @@ class Solver:
     def set_wait_limit(self, seconds: float):
         _check(mprk_set_wait_limit(self.ctx, seconds), "mprk_set_wait_limit")
 
+    def set_tile(self, shape: int):
+        _check(mprk_set_tile(self.ctx, shape), "mprk_set_tile")
+
     def profile(self, on: bool):
         _check(mprk_profile_enable(self.ctx, on), "mprk_profile_enable")
 
@@ -295,6 +396,106 @@ class Solver:
         if getattr(self, "ctx", None):
             mprk_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_state(t, cfg):
+    import torch
+
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("state must be contiguous float64 device tensors")
+
+
+class Batch:
+    """A batch of independent members advanced together (``mprk_batch_*``).
+
+    ``members`` is a sequence of (config, q_lower, q_upper, dt); the state
+    tensors belong to the caller and are updated in place; the workspace
+    tensor belongs to this object."""
+
+    def __init__(self, members, stream=None, exec_mode=None, tile=None):
+        import torch
+
+        if not members:
+            raise ValueError("empty batch")
+        recs = []
+        self._keep = []
+        for cfg, ql, qu, dt in members:
+            _check_state(ql, cfg)
+            _check_state(qu, cfg)
+            if tuple(ql.shape) != (4, cfg.nz_lower, cfg.nx) or \
+                    tuple(qu.shape) != (4, cfg.nz_upper, cfg.nx):
+                raise ValueError("state shapes do not match the configuration")
+            recs.append(mprk_member(cfg, ql.data_ptr(), qu.data_ptr(), float(dt)))
+            self._keep.append((ql, qu))
+        rc, msg = mprk_batch_validate(recs)
+        _check(rc, "mprk_batch_validate: " + msg)
+        self.n = len(recs)
+        self.members = recs
+        nbytes = mprk_batch_workspace_bytes(recs)
+        dev = members[0][1].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc, self.b = mprk_batch_create(recs, self.workspace.data_ptr() + off, nbytes,
+                                       self.stream.cuda_stream)
+        _check(rc, "mprk_batch_create")
+        self.workspace_bytes = nbytes
+        if exec_mode is not None:
+            self.set_exec(exec_mode)
+        if tile is not None:
+            self.set_tile(tile)
+
+    def set_exec(self, mode: int):
+        _check(mprk_batch_set_exec(self.b, mode), "mprk_batch_set_exec")
+
+    def set_tile(self, shape: int):
+        _check(mprk_batch_set_tile(self.b, shape), "mprk_batch_set_tile")
+
+    def set_wait_limit(self, seconds: float):
+        _check(mprk_batch_set_wait_limit(self.b, seconds), "mprk_batch_set_wait_limit")
+
+    def set_dt(self, member: int, dt: float):
+        _check(mprk_batch_set_dt(self.b, member, dt), "mprk_batch_set_dt")
+        self.members[member].dt = float(dt)
+
+    def stable_dts(self, cr=0.5, dn=0.25) -> list:
+        """Step of each member from its current state (the rule of mprk_stable_dt)."""
+        rc, st = mprk_batch_diagnostics(self.b, self.n)
+        _check(rc, "mprk_batch_diagnostics")
+        out = []
+        for m, s in zip(self.members, st):
+            rc, dt = mprk_stable_dt(m.cfg, s, cr, dn)
+            _check(rc, "mprk_stable_dt")
+            out.append(dt)
+        return out
+
+    def tune(self, reps: int = 3):
+        """(milliseconds per slow step for each tile shape, chosen shape)."""
+        rc, ms, best = mprk_batch_tune(self.b, reps)
+        _check(rc, "mprk_batch_tune")
+        return ms, best
+
+    def run(self, nsteps: int, check_every: int = 0) -> list:
+        rc, st = mprk_batch_run(self.b, self.n, nsteps, check_every)
+        _check(rc, "mprk_batch_run")
+        return [x.as_dict() for x in st]
+
+    def diagnostics(self, check=True) -> list:
+        rc, st = mprk_batch_diagnostics(self.b, self.n)
+        if check:
+            _check(rc, "mprk_batch_diagnostics")
+        return [x.as_dict() for x in st]
+
+    def close(self):
+        if getattr(self, "b", None):
+            mprk_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -88,9 +88,11 @@ def test_workspace_bytes():
 
     def tables(cfg):
         # persistent-execution tables: m*s stage records, one 16-B record and
-        # one counter per fixed 32x16 tile, a member record, the abort flag
-        ntiles = -(-cfg.nx // 32) * (-(-cfg.nz_lower // 16) - (-cfg.nz_upper // 16))
-        return cfg.m * cfg.base_rk * 2048 + ntiles * 20 + 2048
+        # one counter per fixed tile of the shape with the most tiles, a
+        # member record, the abort flag
+        ntiles = max(-(-cfg.nx // tx) * (-(-cfg.nz_lower // tz) - (-cfg.nz_upper // tz))
+                     for tx, tz in ((32, 16), (16, 32), (64, 8), (32, 8)))
+        return cfg.m * cfg.base_rk * 2048 + ntiles * 20 + 4096
 
     for kw in ({}, {"m": 1}, {"base_rk": 3, "n_buffer": 5}, {"fast_is_lower": 0}):
         cfg = _cfg(**kw)
@@ -147,3 +149,53 @@ def test_stable_dt_rule_matches_the_oracle_rule():
         assert dt == pytest.approx(oracle.dt_rule(pb, ql, qu, m), rel=1e-15)
     st.status = 1
     assert mprk.mprk_stable_dt(mprk.config_of_workload(w), st, 0.5, 0.25)[0] == mprk.ENONFINITE
+
+
+def _member(w=None, ql=1 << 20, qu=(1 << 20) + (1 << 24), dt=0.01, **kw):
+    w = w or inputs.small()
+    return mprk.mprk_member(mprk.config_of_workload(w, **kw), ql, qu, dt)
+
+
+def test_batch_validation_rules():
+    a = _member()
+    b = _member(ql=3 << 24, qu=4 << 24, m=4, base_rk=3, n_buffer=5)
+    assert mprk.mprk_batch_validate([a, b])[0] == mprk.OK
+    assert mprk.mprk_batch_validate([])[0] == mprk.EINVAL
+    assert mprk.mprk_batch_validate([a, _member(ql=3 << 24, qu=4 << 24, flux_bits=32)])[0] == mprk.EINVAL
+    assert mprk.mprk_batch_validate([a, _member(ql=3 << 24, qu=4 << 24, dt=0.0)])[0] == mprk.EINVAL
+    rc, msg = mprk.mprk_batch_validate([a, _member(ql=3 << 24, qu=4 << 24, m=0)])
+    assert rc == mprk.EINVAL and "member 1" in msg
+
+
+def test_batch_workspace_covers_every_member():
+    ws = [inputs.small(), inputs.small().with_(nx=37, nz_lower=33, nz_upper=21, base=3, m=4,
+                                               n_buffer=5)]
+    mem = [_member(w, ql=(2 * i + 1) << 24, qu=(2 * i + 2) << 24, base_rk=w.base, m=w.m,
+                   n_buffer=w.n_buffer) for i, w in enumerate(ws)]
+    total = mprk.mprk_batch_workspace_bytes(mem)
+    single = sum(mprk.mprk_workspace_bytes(m.cfg) for m in mem)
+    # member scratch is the single-context workspace minus its persistent tables
+    assert total > 0.5 * single
+    assert mprk.mprk_batch_workspace_bytes(mem[:1]) < total
+
+
+def test_batch_create_rejects_overlap_and_small_workspace():
+    a = _member()
+    b = _member(ql=(1 << 20) + 4096, qu=5 << 24)        # overlaps a's lower state
+    need = mprk.mprk_batch_workspace_bytes([a, b])
+    fake = 1 << 30
+    assert mprk.mprk_batch_create([a, b], fake, need, None)[0] == mprk.EINVAL
+    c = _member(ql=5 << 24, qu=6 << 24)
+    need = mprk.mprk_batch_workspace_bytes([a, c])
+    assert mprk.mprk_batch_create([a, c], fake, need - 256, None)[0] == mprk.EWORKSPACE
+    assert mprk.mprk_batch_create([a, c], fake + 8, need, None)[0] == mprk.EWORKSPACE
+    lib = mprk.load()
+    assert lib.mprk_batch_run(None, 1, 0, None) == mprk.EINVAL
+    assert lib.mprk_batch_set_tile(None, 0) == mprk.EINVAL
+    assert lib.mprk_batch_destroy(None) == mprk.EINVAL
+
+
+def test_tile_shape_and_exec_arguments_checked():
+    lib = mprk.load()
+    assert lib.mprk_set_tile(None, 0) == mprk.EINVAL
+    assert lib.mprk_set_exec(None, mprk.EXEC_GRAPH) == mprk.EINVAL
