@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux run")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
+    ap.add_argument("--ensemble-members", type=int, default=64)
+    ap.add_argument("--ensemble-steps", type=int, default=None, help="default: the members' 500")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -332,7 +335,131 @@ def main():
         print("# cpu oracle: %d steps in %.1f s on %d threads" % (n, el, oracle.threads()),
               file=sys.stderr, flush=True)
 
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_leg(args, torch, dev)
+
     print(json.dumps(out), flush=True)
+
+
+def ensemble_leg(args, torch, dev):
+    """Batched uneven ensemble (FP32 face fluxes, FP64 state).  Tile shape from
+    the autotuner; every member advanced together with adaptive steps (each
+    member's step reset from its own state every CH slow steps); the same
+    members then run single-rate with each member's step divided by its m,
+    chunk by chunk, so both reach the same times."""
+    from paper_2202_11890_amd import costmodel, inputs, mprk
+
+    CH = 20
+    ws = inputs.ensemble(args.ensemble_members)
+    K = args.ensemble_steps if args.ensemble_steps is not None else ws[0].steps
+    K = max(CH, K // CH * CH)
+    init = [inputs.initial_state(w) for w in ws]
+    tens = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)) for a, b in init]
+    keep = [(a.clone(), b.clone()) for a, b in tens]
+    cr, dn = ws[0].cfl, ws[0].dnum
+
+    def restore():
+        for (a, b), (c, d) in zip(tens, keep):
+            a.copy_(c)
+            b.copy_(d)
+        torch.cuda.synchronize()
+
+    batch = mprk.Batch([(mprk.config_of_workload(w, flux_bits=32), a, b, 1.0)
+                        for w, (a, b) in zip(ws, tens)])
+    dts0 = batch.stable_dts(cr, dn)
+
+    def reset_dts(bt, scale=None):
+        for i, d in enumerate(dts0):
+            bt.set_dt(i, d if scale is None else d / scale[i])
+
+    reset_dts(batch)
+    tuner_ms, best = batch.tune(3)
+    print("# ensemble tuner (ms per slow step): %s -> %s" % (
+        ", ".join("%s %.3f" % (mprk.TILE_NAMES[k], v) for k, v in enumerate(tuner_ms)),
+        mprk.TILE_NAMES[best]), file=sys.stderr, flush=True)
+    cs = 0
+    cells = 0
+    for w in ws:
+        nF, nB, nS = costmodel.partition_counts(w.nx, w.nz_lower, w.nz_upper, w.n_buffer)
+        cs += costmodel.mprk_cell_stages(nF, nB, nS, w.m, w.base)
+        cells += w.nx * (w.nz_lower + w.nz_upper)
+
+    def timed(bt, mode, nsteps, hist=None, chunk=CH):
+        bt.set_exec(mode)
+        bt.set_adaptive(0.0, dn)
+        bt.run(1, check_every=0)
+        restore()
+        reset_dts(bt)
+        bt.set_adaptive(cr, dn)
+        bad = 0
+        t0 = time.perf_counter()
+        for _ in range(nsteps // chunk):
+            if hist is not None:
+                hist.append(bt.dts())
+            st = bt.run(chunk, check_every=chunk)
+            bad += sum(x["status"] for x in st)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, bad
+
+    hist = []
+    t_graph, bad = timed(batch, mprk.EXEC_GRAPH, K, hist)
+    final = [(a.cpu().numpy(), b.cpu().numpy()) for a, b in tens]
+    k_short = max(CH, K // 10 // CH * CH)
+    t_launch, _ = timed(batch, mprk.EXEC_LAUNCH, K)
+    t_pers, _ = timed(batch, mprk.EXEC_PERSISTENT, k_short)
+    batch.close()
+    rate = cs * K / t_graph
+    print("# ensemble: %d members, %d steps in %.3f s (graph), %.3e cell-stage/s" % (
+        len(ws), K, t_graph, rate), file=sys.stderr, flush=True)
+
+    # single rate at each member's fast step (its MPRK step / m, replayed
+    # chunk by chunk), one batch per value of m
+    t_sr = 0.0
+    cs_sr = 0
+    sr_final = [None] * len(ws)
+    for mval in sorted(set(w.m for w in ws)):
+        idx = [i for i, w in enumerate(ws) if w.m == mval]
+        restore()
+        sb = mprk.Batch([(mprk.config_of_workload(ws[i], flux_bits=32, m=1), tens[i][0], tens[i][1],
+                          dts0[i] / mval) for i in idx], exec_mode=mprk.EXEC_GRAPH, tile=best)
+        sb.run(1, check_every=0)
+        restore()
+        t0 = time.perf_counter()
+        for h in hist:
+            for j, i in enumerate(idx):
+                sb.set_dt(j, h[i] / mval)
+            sb.run(CH * mval, check_every=CH * mval)
+        torch.cuda.synchronize()
+        t_sr += time.perf_counter() - t0
+        sb.close()
+        for i in idx:
+            sr_final[i] = (tens[i][0].cpu().numpy(), tens[i][1].cpu().numpy())
+            w = ws[i]
+            cs_sr += costmodel.sr_cell_stages(w.nx * (w.nz_lower + w.nz_upper), mval, w.base)
+    diff = 0.0
+    for (a, b), (c, d) in zip(final, sr_final):
+        for x, y in ((a, c), (b, d)):
+            scale = np.abs(y).max(axis=(1, 2))
+            scale[1:3] = max(scale[1], scale[2])
+            diff = max(diff, float((np.abs(x - y).max(axis=(1, 2)) / scale).max()))
+    restore()
+    print("# ensemble single rate: %.3f s, time-to-solution speedup %.3f" % (t_sr, t_sr / t_graph),
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "%d uneven two-domain members (nx 128..512, nz 64..256, m in {2,4,8}), MPRK2, "
+                    "FP32 flux / FP64 state, adaptive steps every %d" % (len(ws), CH),
+        "cells": cells, "steps": K, "cell_stages_per_step": cs,
+        "value": max(rate, cs * K / t_launch), "unit": "cell-stage updates/s",
+        "best_mode": "graph" if rate >= cs * K / t_launch else "launch",
+        "seconds_graph": t_graph, "seconds_launch": t_launch, "status_bad": bad,
+        "tile": mprk.TILE_NAMES[best],
+        "tuner_ms_per_step": {mprk.TILE_NAMES[k]: v for k, v in enumerate(tuner_ms)},
+        "modes": {"graph": rate, "launch": cs * K / t_launch,
+                  "persistent": cs * k_short / t_pers, "steps_persistent": k_short},
+        "single_rate": {"seconds": t_sr, "value": cs_sr * K / t_sr,
+                        "time_to_solution_speedup": t_sr / t_graph,
+                        "max_rel_diff_mprk_vs_single_rate": diff},
+    }
 
 
 if __name__ == "__main__":

@@ -286,6 +286,17 @@ int mprk_batch_tune(mprk_batch* batch, int32_t reps, double* ms_out, int32_t* be
  * to the check point). */
 int mprk_batch_run(mprk_batch* batch, int64_t nsteps, int64_t check_every, mprk_stats* out);
 
+/* Adaptive steps: when cr > 0, at every check point of mprk_batch_run each
+ * member's slow step is reset to mprk_stable_dt(cfg, its stats, cr, dn) of
+ * its current state (the rule of the initial step, tracking states that
+ * change, e.g. slow cells heated through the interface).  cr = 0 (the
+ * default) keeps the steps fixed.  A member's step sequence depends only on
+ * its own state. */
+int mprk_batch_set_adaptive(mprk_batch* batch, double cr, double dn);
+
+/* Current slow step of a member. */
+int mprk_batch_get_dt(mprk_batch* batch, int32_t member, double* dt);
+
 /* Per-member reductions on the current states (n entries); synchronises. */
 int mprk_batch_diagnostics(mprk_batch* batch, mprk_stats* out);
 

@@ -322,8 +322,8 @@ StageArgs proxy_args(const Member& mb, double dt, int k, int j, int shape)
     return a;
 }
 
-// Device reductions of one member: totals, stability measures, status.
-int member_reduce_launch(const Member& mb, hipStream_t stream, double* host_final)
+// Reduction record of one member (partials in its scratch; finals at final_).
+ReduceArgs member_reduce_args(const Member& mb, double* final_)
 {
     const mprk_config& g = mb.cfg;
     ReduceArgs r;
@@ -342,7 +342,14 @@ int member_reduce_launch(const Member& mb, hipStream_t stream, double* host_fina
     r.gamma = g.gamma;
     r.gm1 = g.gamma - 1.0;
     r.partial = (double*)(mb.ws + mb.lay.off_partial);
-    r.final_ = (double*)(mb.ws + mb.lay.off_final);
+    r.final_ = final_;
+    return r;
+}
+
+// Device reductions of one member: totals, stability measures, status.
+int member_reduce_launch(const Member& mb, hipStream_t stream, double* host_final)
+{
+    const ReduceArgs r = member_reduce_args(mb, (double*)(mb.ws + mb.lay.off_final));
     if (launch_reduce(r, stream) != hipSuccess) return MPRK_EHIP;
     if (hipMemcpyAsync(host_final, r.final_, 2 * RED_FIELDS * sizeof(double), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
@@ -505,9 +512,13 @@ struct mprk_batch {
     std::vector<int> slot_stage;              // [member][slot]: stage record or -1
     // device tables (offsets into ws)
     size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    size_t off_red, off_finals;
+    bool red_ready = false;
+    std::vector<ReduceArgs> h_red;
     int max_tiles = 0;
     // host tables for the current shape
     int tab_shape = -1;
+    bool rec_dirty = false;                   // steps changed: stage records to rewrite
     std::vector<StageArgs> h_tab, h_proxy;
     std::vector<BatchEntry> h_ent;            // [slot][member] (first count entries used)
     std::vector<int> slot_count, slot_blocks;
@@ -523,6 +534,8 @@ struct mprk_batch {
     struct NodeArgs { const StageArgs* tab; const BatchEntry* ent; int nent; int nblocks; };
     std::vector<NodeArgs> g_vals;
     std::vector<double> host_final;           // [member][2*RED_FIELDS]
+    double adapt_cr = 0.0, adapt_dn = 0.0;    // adaptive steps at check points (cr 0: off)
+    std::vector<mprk_stats> chk;              // stats of the last check
 };
 
 namespace {
@@ -686,6 +699,7 @@ int run_reduce(mprk_ctx* c, mprk_stats* out)
 struct BatchLayout {
     std::vector<size_t> core_off;
     size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    size_t off_red, off_finals;
     int nslots, total_ms, max_tiles;
     size_t total;
 };
@@ -747,6 +761,10 @@ bool batch_layout(const mprk_member* mem, int32_t n, BatchLayout* L)
     off += round_up((size_t)n * sizeof(MemberRun));
     L->off_pdone = off;
     off += round_up((size_t)(tiles + 1) * sizeof(int32_t));
+    L->off_red = off;
+    off += round_up((size_t)n * sizeof(ReduceArgs));
+    L->off_finals = off;
+    off += round_up((size_t)n * 2 * RED_FIELDS * sizeof(double));
     L->total = off;
     return true;
 }
@@ -755,9 +773,32 @@ bool batch_layout(const mprk_member* mem, int32_t n, BatchLayout* L)
 // Member i's stage p (0-based within a slow step) runs in slot
 // floor(p * nslots / (m_i s_i)), which spreads each member's stages evenly
 // over the slow step's launches.
+// Stage records only (after a change of steps; the launch layout and the
+// graph, which reference the record table by address, stay valid).
+int batch_records(mprk_batch* b)
+{
+    b->h_tab.clear();
+    b->h_proxy.clear();
+    for (int i = 0; i < b->n; ++i) {
+        const Member& mb = b->mb[i];
+        for (int k = 1; k <= mb.cfg.m; ++k)
+            for (int j = 1; j <= mb.lay.s; ++j) {
+                b->h_tab.push_back(stage_args(mb, b->dt[i], k, j, b->shape));
+                b->h_proxy.push_back(proxy_args(mb, b->dt[i], k, j, b->shape));
+            }
+    }
+    if (hipMemcpyAsync(b->ws + b->off_tab, b->h_tab.data(), b->h_tab.size() * sizeof(StageArgs),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->ws + b->off_proxy, b->h_proxy.data(), b->h_proxy.size() * sizeof(StageArgs),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return MPRK_EHIP;
+    b->rec_dirty = false;
+    return MPRK_OK;
+}
+
 int batch_tables(mprk_batch* b)
 {
-    if (b->tab_shape == b->shape) return MPRK_OK;
+    if (b->tab_shape == b->shape) return b->rec_dirty ? batch_records(b) : MPRK_OK;
     const int n = b->n, L = b->nslots;
     b->h_tab.clear();
     b->h_proxy.clear();
@@ -820,7 +861,8 @@ int batch_tables(mprk_batch* b)
                        hipMemcpyHostToDevice, st) != hipSuccess)
         return MPRK_EHIP;
     b->tab_shape = b->shape;
-    b->graph.reset();           // node arguments point at the tables just rewritten
+    b->rec_dirty = false;
+    b->graph.reset();           // block counts per launch may differ for a new shape
     return MPRK_OK;
 }
 
@@ -922,14 +964,26 @@ int batch_advance(mprk_batch* b, int64_t nsteps)
     return rc;
 }
 
+// Reductions of every member in two launches and one copy back.
 int batch_reduce(mprk_batch* b, mprk_stats* out)
 {
     const int n = b->n;
-    b->host_final.resize((size_t)n * 2 * RED_FIELDS);
-    for (int i = 0; i < n; ++i) {
-        int rc = member_reduce_launch(b->mb[i], b->stream, b->host_final.data() + (size_t)i * 2 * RED_FIELDS);
-        if (rc != MPRK_OK) return rc;
+    const size_t nf = (size_t)n * 2 * RED_FIELDS;
+    b->host_final.resize(nf);
+    double* finals = (double*)(b->ws + b->off_finals);
+    if (!b->red_ready) {
+        b->h_red.resize(n);
+        for (int i = 0; i < n; ++i) b->h_red[i] = member_reduce_args(b->mb[i], finals + (size_t)i * 2 * RED_FIELDS);
+        if (hipMemcpyAsync(b->ws + b->off_red, b->h_red.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice,
+                           b->stream) != hipSuccess)
+            return MPRK_EHIP;
+        b->red_ready = true;
     }
+    if (launch_reduce_batch((const ReduceArgs*)(b->ws + b->off_red), n, b->stream) != hipSuccess)
+        return MPRK_EHIP;
+    if (hipMemcpyAsync(b->host_final.data(), finals, nf * sizeof(double), hipMemcpyDeviceToHost, b->stream) !=
+        hipSuccess)
+        return MPRK_EHIP;
     int32_t aborted = 0;
     if (b->exec == MPRK_EXEC_PERSISTENT && b->tab_shape >= 0) {
         int ntiles = 0;
@@ -1284,6 +1338,8 @@ int mprk_batch_create(const mprk_member* members, int32_t n, void* workspace, si
     b->off_ptiles = L.off_ptiles;
     b->off_pmember = L.off_pmember;
     b->off_pdone = L.off_pdone;
+    b->off_red = L.off_red;
+    b->off_finals = L.off_finals;
     *out = b;
     return MPRK_OK;
 }
@@ -1307,8 +1363,7 @@ int mprk_batch_set_dt(mprk_batch* b, int32_t member, double dt)
     if (!b || member < 0 || member >= b->n || !(dt > 0) || !std::isfinite(dt)) return MPRK_EINVAL;
     if (b->dt[member] != dt) {
         b->dt[member] = dt;
-        b->tab_shape = -1;      // stage records carry dt: rebuild tables and graph
-        b->graph.reset();
+        b->rec_dirty = true;    // stage records carry dt
     }
     return MPRK_OK;
 }
@@ -1359,9 +1414,26 @@ int mprk_batch_tune(mprk_batch* b, int32_t reps, double* ms_out, int32_t* best)
     return rc;
 }
 
+int mprk_batch_set_adaptive(mprk_batch* b, double cr, double dn)
+{
+    if (!b || !(cr >= 0.0) || !std::isfinite(cr) || (cr > 0.0 && !(dn > 0.0 && std::isfinite(dn))))
+        return MPRK_EINVAL;
+    b->adapt_cr = cr;
+    b->adapt_dn = dn;
+    return MPRK_OK;
+}
+
+int mprk_batch_get_dt(mprk_batch* b, int32_t member, double* dt)
+{
+    if (!b || !dt || member < 0 || member >= b->n) return MPRK_EINVAL;
+    *dt = b->dt[member];
+    return MPRK_OK;
+}
+
 int mprk_batch_run(mprk_batch* b, int64_t nsteps, int64_t check_every, mprk_stats* out)
 {
     if (!b || nsteps < 0) return MPRK_EINVAL;
+    b->chk.resize(b->n);
     if (nsteps == 0) return batch_reduce(b, out);
     const int64_t chunk = check_every > 0 ? check_every : nsteps;
     for (int64_t done = 0; done < nsteps;) {
@@ -1369,8 +1441,20 @@ int mprk_batch_run(mprk_batch* b, int64_t nsteps, int64_t check_every, mprk_stat
         int rc = batch_advance(b, k);
         if (rc != MPRK_OK) return rc;
         done += k;
-        rc = batch_reduce(b, out);
+        rc = batch_reduce(b, b->chk.data());
+        if (out) std::copy(b->chk.begin(), b->chk.end(), out);
         if (rc != MPRK_OK) return rc;
+        if (b->adapt_cr > 0.0) {
+            // Each member's next step from its own state: a member's step
+            // sequence does not depend on the rest of the batch.
+            for (int i = 0; i < b->n; ++i) {
+                double dt = 0.0;
+                rc = mprk_stable_dt(&b->mb[i].cfg, &b->chk[i], b->adapt_cr, b->adapt_dn, &dt);
+                if (rc != MPRK_OK) return rc;
+                rc = mprk_batch_set_dt(b, i, dt);
+                if (rc != MPRK_OK) return rc;
+            }
+        }
     }
     return MPRK_OK;
 }

@@ -165,5 +165,6 @@ hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int sh
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
 int persistent_blocks_per_cu(bool flux32, int shape);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_reduce_batch(const ReduceArgs* tab, int n, hipStream_t s);
 
 }  // namespace mprk

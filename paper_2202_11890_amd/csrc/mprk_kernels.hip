@@ -751,10 +751,8 @@ __device__ void block_tree(RedVal& mine, double* sh)
     red_load(sh, mine);
 }
 
-__global__ __launch_bounds__(RED_THREADS) void reduce_partial(const ReduceArgs A)
+__device__ __forceinline__ void reduce_partial_body(const ReduceArgs& A, int dom, int blk, double* sh)
 {
-    __shared__ double sh[RED_THREADS * RED_FIELDS];
-    const int dom = blockIdx.y;
     const double* q = A.q[dom];
     const int n = A.nz[dom] * A.nx;
     const double inv_dz = A.inv_dz[dom], vc = A.visc_coef[dom];
@@ -762,7 +760,7 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_partial(const ReduceArgs A
 #pragma unroll
     for (int v = 0; v < NV; ++v) { m.s[v] = 0.0; m.e[v] = 0.0; }
     m.lam = m.cour = m.vis = m.bad = 0.0;
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+    for (int i = blk * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
         const double rho = q[i], mx = q[(size_t)n + i], mz = q[2 * (size_t)n + i],
                      en = q[3 * (size_t)n + i];
         two_sum(m.s[0], m.e[0], rho);
@@ -785,18 +783,42 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_partial(const ReduceArgs A
         }
     }
     block_tree(m, sh);
-    if (threadIdx.x == 0) red_store(A.partial + ((size_t)dom * RED_BLOCKS + blockIdx.x) * RED_FIELDS, m);
+    if (threadIdx.x == 0) red_store(A.partial + ((size_t)dom * RED_BLOCKS + blk) * RED_FIELDS, m);
 }
 
-__global__ __launch_bounds__(RED_THREADS) void reduce_final(const ReduceArgs A)
+__device__ __forceinline__ void reduce_final_body(const ReduceArgs& A, int dom, double* sh)
 {
     static_assert(RED_BLOCKS == RED_THREADS, "one partial per thread");
-    __shared__ double sh[RED_THREADS * RED_FIELDS];
-    const int dom = blockIdx.x;
     RedVal m;
     red_load(A.partial + ((size_t)dom * RED_BLOCKS + threadIdx.x) * RED_FIELDS, m);
     block_tree(m, sh);
     if (threadIdx.x == 0) red_store(A.final_ + (size_t)dom * RED_FIELDS, m);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void reduce_partial(const ReduceArgs A)
+{
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    reduce_partial_body(A, blockIdx.y, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void reduce_final(const ReduceArgs A)
+{
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    reduce_final_body(A, blockIdx.x, sh);
+}
+
+// Every member of a batch at once: blockIdx.z (partial) / blockIdx.y (final)
+// selects the member's record.
+__global__ __launch_bounds__(RED_THREADS) void reduce_partial_batch(const ReduceArgs* __restrict__ tab)
+{
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    reduce_partial_body(tab[blockIdx.z], blockIdx.y, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void reduce_final_batch(const ReduceArgs* __restrict__ tab)
+{
+    __shared__ double sh[RED_THREADS * RED_FIELDS];
+    reduce_final_body(tab[blockIdx.y], blockIdx.x, sh);
 }
 
 using S0 = Shape<32, 16>;
@@ -875,6 +897,16 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceArgs* tab, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_partial_batch, dim3(RED_BLOCKS, 2, n), dim3(RED_THREADS), 0, s, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_batch, dim3(2, n), dim3(RED_THREADS), 0, s, tab);
     return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ EXPORTS = ("mprk_validate", "mprk_workspace_bytes", "mprk_create", "mprk_set_str
            "mprk_profile_enable", "mprk_profile_take", "mprk_destroy", "mprk_strerror",
            "mprk_batch_validate", "mprk_batch_workspace_bytes", "mprk_batch_create",
            "mprk_batch_set_exec", "mprk_batch_set_tile", "mprk_batch_set_wait_limit", "mprk_batch_set_dt",
+           "mprk_batch_set_adaptive", "mprk_batch_get_dt",
            "mprk_batch_tune", "mprk_batch_run", "mprk_batch_diagnostics", "mprk_batch_destroy")
 
 _lib = None
@@ -139,6 +140,8 @@ def load(path: str = LIB_PATH):
     lib.mprk_batch_set_tile.argtypes = [V, ctypes.c_int]
     lib.mprk_batch_set_wait_limit.argtypes = [V, ctypes.c_double]
     lib.mprk_batch_set_dt.argtypes = [V, ctypes.c_int32, ctypes.c_double]
+    lib.mprk_batch_set_adaptive.argtypes = [V, ctypes.c_double, ctypes.c_double]
+    lib.mprk_batch_get_dt.argtypes = [V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.mprk_batch_tune.argtypes = [V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int32)]
     lib.mprk_batch_run.argtypes = [V, ctypes.c_int64, ctypes.c_int64, S]
@@ -271,6 +274,16 @@ def mprk_batch_set_wait_limit(b, seconds):
 
 def mprk_batch_set_dt(b, member, dt):
     return load().mprk_batch_set_dt(b, int(member), float(dt))
+
+
+def mprk_batch_set_adaptive(b, cr, dn):
+    return load().mprk_batch_set_adaptive(b, float(cr), float(dn))
+
+
+def mprk_batch_get_dt(b, member):
+    dt = ctypes.c_double()
+    rc = load().mprk_batch_get_dt(b, int(member), ctypes.byref(dt))
+    return rc, dt.value
 
 
 def mprk_batch_tune(b, reps):
@@ -463,6 +476,17 @@ class Batch:
     def set_dt(self, member: int, dt: float):
         _check(mprk_batch_set_dt(self.b, member, dt), "mprk_batch_set_dt")
         self.members[member].dt = float(dt)
+
+    def set_adaptive(self, cr: float, dn: float = 0.25):
+        _check(mprk_batch_set_adaptive(self.b, cr, dn), "mprk_batch_set_adaptive")
+
+    def dts(self) -> list:
+        out = []
+        for i in range(self.n):
+            rc, dt = mprk_batch_get_dt(self.b, i)
+            _check(rc, "mprk_batch_get_dt")
+            out.append(dt)
+        return out
 
     def stable_dts(self, cr=0.5, dn=0.25) -> list:
         """Step of each member from its current state (the rule of mprk_stable_dt)."""

@@ -199,3 +199,9 @@ def test_tile_shape_and_exec_arguments_checked():
     lib = mprk.load()
     assert lib.mprk_set_tile(None, 0) == mprk.EINVAL
     assert lib.mprk_set_exec(None, mprk.EXEC_GRAPH) == mprk.EINVAL
+
+
+def test_batch_adaptive_arguments_checked():
+    lib = mprk.load()
+    assert lib.mprk_batch_set_adaptive(None, 0.5, 0.25) == mprk.EINVAL
+    assert lib.mprk_batch_get_dt(None, 0, None) == mprk.EINVAL

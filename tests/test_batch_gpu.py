@@ -197,3 +197,31 @@ def test_batch_reports_a_bad_member():
     st = b.diagnostics(check=False)
     assert [s["status"] for s in st] == [0, 1, 0]
     b.close()
+
+
+def test_adaptive_steps_follow_each_members_state():
+    """Adaptive steps: the run equals running chunk by chunk and resetting
+    every member's step from its own diagnostics in between."""
+    sts = states(MEMBERS)
+    tens = [(dev(ql), dev(qu)) for _, ql, qu, _ in sts]
+    mem = [(mprk.config_of_workload(w), tl, tu, dt) for (w, _, _, dt), (tl, tu) in zip(sts, tens)]
+    b = mprk.Batch(mem, exec_mode=mprk.EXEC_GRAPH)
+    b.set_adaptive(0.5, 0.25)
+    b.run(9, check_every=3)
+    dts = b.dts()
+    torch.cuda.synchronize()
+    got = [(tl.cpu().numpy(), tu.cpu().numpy()) for tl, tu in tens]
+    b.close()
+    tens = [(dev(ql), dev(qu)) for _, ql, qu, _ in sts]
+    mem = [(mprk.config_of_workload(w), tl, tu, dt) for (w, _, _, dt), (tl, tu) in zip(sts, tens)]
+    r = mprk.Batch(mem)
+    for _ in range(3):
+        r.run(3)
+        for i, d in enumerate(r.stable_dts(0.5, 0.25)):
+            r.set_dt(i, d)
+    assert r.dts() == dts
+    torch.cuda.synchronize()
+    ref = [(tl.cpu().numpy(), tu.cpu().numpy()) for tl, tu in tens]
+    r.close()
+    assert all(same(a, c) for a, c in zip(ref, got))
+    assert any(d != s[3] for d, s in zip(dts, sts))
