@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux run")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
     ap.add_argument("--ensemble-members", type=int, default=64)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-requests", type=int, default=120)
+    ap.add_argument("--serving-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--ensemble-steps", type=int, default=None, help="default: the members' 500")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -337,6 +341,8 @@ def main():
 
     if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(args, torch, dev)
+    if not args.no_serving:
+        out["serving"] = serving_leg(args, torch, dev)
 
     print(json.dumps(out), flush=True)
 
@@ -459,6 +465,52 @@ def ensemble_leg(args, torch, dev):
         "single_rate": {"seconds": t_sr, "value": cs_sr * K / t_sr,
                         "time_to_solution_speedup": t_sr / t_graph,
                         "max_rel_diff_mprk_vs_single_rate": diff},
+    }
+
+
+def serving_leg(args, torch, dev):
+    """Continuous-batching server: saturated capacity (every request waiting at
+    t = 0), then Poisson arrivals at a fraction of that capacity; p50/p99
+    request latency and aggregate cell-stage updates/s."""
+    from paper_2202_11890_amd import costmodel, inputs, mprk, serving
+
+    n = args.serving_requests
+    budget = 32 << 30
+
+    def make(rate, seed):
+        reqs, cs = [], {}
+        for i, (t, w) in enumerate(inputs.serving_requests(n, rate, seed)):
+            ql, qu = inputs.initial_state(w)
+            reqs.append(serving.Request(i, mprk.config_of_workload(w), ql, qu, w.steps,
+                                        t if rate > 0 else 0.0))
+            nF, nB, nS = costmodel.partition_counts(w.nx, w.nz_lower, w.nz_upper, w.n_buffer)
+            cs[i] = costmodel.mprk_cell_stages(nF, nB, nS, w.m, w.base) * w.steps
+        return reqs, cs
+
+    reqs, cs = make(1.0, 11)
+    for r in reqs:
+        r.arrival = 0.0
+    srv = serving.Server(dev, budget, max_slots=64, chunk=10)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    sat = serving.summarize(res, cs, time.perf_counter() - t0)
+    capacity = sat["requests"] / sat["makespan_s"]
+    rate = args.serving_load * capacity
+    reqs, cs = make(rate, 12)
+    srv = serving.Server(dev, budget, max_slots=64, chunk=10)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    load = serving.summarize(res, cs, time.perf_counter() - t0)
+    load["arrival_rate_per_s"] = rate
+    load["mean_active"] = float(np.mean([a for _, a, _ in srv.log])) if srv.log else 0.0
+    load["batch_rebuilds"] = srv.rebuilds
+    print("# serving: capacity %.1f req/s (%.3e cell-stage/s); at %.1f req/s p50 %.3f s p99 %.3f s" % (
+        capacity, sat["cell_stage_updates_per_s"], rate, load["latency_s"]["p50"],
+        load["latency_s"]["p99"]), file=sys.stderr, flush=True)
+    return {
+        "workload": "%d requests, nx log-uniform 64..1024 (nz = nx/2), 50..500 slow steps, m in {2,4}, "
+                    "MPRK2, FP64; budget %d GiB, 64 slots, 10-step chunks" % (n, budget >> 30),
+        "saturated": sat, "capacity_requests_per_s": capacity, "poisson": load,
     }
 
 

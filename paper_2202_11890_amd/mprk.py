@@ -510,6 +510,12 @@ class Batch:
         _check(rc, "mprk_batch_run")
         return [x.as_dict() for x in st]
 
+    def run_status(self, nsteps: int, check_every: int = 0):
+        """Like run, but returns (status code, per-member stats) instead of
+        raising when a member's state is bad."""
+        rc, st = mprk_batch_run(self.b, self.n, nsteps, check_every)
+        return rc, [x.as_dict() for x in st]
+
     def diagnostics(self, check=True) -> list:
         rc, st = mprk_batch_diagnostics(self.b, self.n)
         if check:

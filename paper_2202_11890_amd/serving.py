@@ -1,0 +1,195 @@
+"""Serving loop with continuous batching over the batch C ABI.
+
+Requests (a two-domain problem, its initial state and a number of slow
+steps) arrive over time.  The server keeps every admitted request's state
+resident in device memory and advances all of them together as one batch
+(``mprk_batch_*``), a chunk of slow steps at a time.  Between chunks,
+finished requests leave (their state is copied back and their memory
+released) and requests that have arrived are admitted while the device
+memory budget (state + workspace share, ``mprk_batch_workspace_bytes``) and
+the slot count allow, so new work joins work already on the device.
+
+A request's arithmetic is that of a batch member: it does not depend on what
+else is in the batch or on how its steps are split into chunks (each member
+keeps the fixed slow step computed from its own initial state), so every
+result is bit-identical to the same request run alone.
+
+All computation runs in the HIP library; this module schedules.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import mprk
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    cfg: "mprk.mprk_config"
+    q_lower: np.ndarray            # initial state, float64 [4, nz_lower, nx]
+    q_upper: np.ndarray
+    steps: int                     # slow steps to run
+    arrival: float = 0.0           # seconds after the server starts
+    dt: Optional[float] = None     # slow step (None: the stable-step rule of its initial state)
+    cell_stages_per_step: int = 0  # for the throughput figure (optional)
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    q_lower: np.ndarray
+    q_upper: np.ndarray
+    dt: float
+    steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    status: int
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint(cfg) -> int:
+    """Device bytes a request holds while admitted: its two state arrays plus
+    its share of a batch workspace (the workspace of a one-member batch)."""
+    state = 8 * 4 * cfg.nx * (cfg.nz_lower + cfg.nz_upper)
+    probe = mprk.mprk_member(cfg, 1 << 20, (1 << 20) + state, 1.0)
+    return state + mprk.mprk_batch_workspace_bytes([probe])
+
+
+class _Active:
+    __slots__ = ("req", "ql", "qu", "dt", "done", "admitted", "bytes")
+
+    def __init__(self, req, ql, qu, dt, admitted, nbytes):
+        self.req, self.ql, self.qu, self.dt = req, ql, qu, dt
+        self.done = 0
+        self.admitted = admitted
+        self.bytes = nbytes
+
+
+class Server:
+    """Continuous-batching server.
+
+    budget_bytes : device memory the admitted requests may hold.
+    max_slots    : most requests in the batch at once.
+    chunk        : slow steps between scheduling points.
+    cr, dn       : step rule for requests without dt (mprk_stable_dt).
+    """
+
+    def __init__(self, device, budget_bytes: int, max_slots: int = 64, chunk: int = 10,
+                 exec_mode: int = mprk.EXEC_LAUNCH, tile: Optional[int] = None, cr: float = 0.5,
+                 dn: float = 0.25, clock: Callable[[], float] = time.perf_counter):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.chunk = int(chunk)
+        self.exec_mode = exec_mode
+        self.tile = tile
+        self.cr, self.dn = cr, dn
+        self.clock = clock
+        self.batch = None
+        self.dirty = False
+        self.active: List[_Active] = []
+        self.used = 0
+        self.rebuilds = 0
+        self.log = []                # (time, active count, bytes held) after each chunk
+
+    # -- helpers -----------------------------------------------------------
+    def _stable_dt(self, cfg, ql, qu) -> float:
+        b = mprk.Batch([(cfg, ql, qu, 1.0)])
+        dt = b.stable_dts(self.cr, self.dn)[0]
+        b.close()
+        return dt
+
+    def _rebuild(self):
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+        if self.active:
+            self.batch = mprk.Batch([(a.req.cfg, a.ql, a.qu, a.dt) for a in self.active],
+                                    exec_mode=self.exec_mode, tile=self.tile)
+            self.rebuilds += 1
+        self.dirty = False
+
+    # -- main loop ---------------------------------------------------------
+    def run(self, requests: List[Request]) -> List[Result]:
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in pending:
+            if footprint(r.cfg) > self.budget:
+                raise ValueError("request %d needs more memory than the whole budget" % r.rid)
+        results: List[Result] = []
+        t0 = self.clock()
+        while pending or self.active:
+            now = self.clock() - t0
+            # admit, in arrival order, while memory and slots allow
+            while pending and pending[0].arrival <= now and len(self.active) < self.max_slots:
+                r = pending[0]
+                need = footprint(r.cfg)
+                if self.used + need > self.budget:
+                    break
+                pending.pop(0)
+                ql = torch.from_numpy(np.ascontiguousarray(r.q_lower)).to(self.device)
+                qu = torch.from_numpy(np.ascontiguousarray(r.q_upper)).to(self.device)
+                dt = r.dt if r.dt is not None else self._stable_dt(r.cfg, ql, qu)
+                self.active.append(_Active(r, ql, qu, dt, self.clock() - t0, need))
+                self.used += need
+                self.dirty = True
+            if not self.active:
+                # idle until the next arrival
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                continue
+            if self.dirty or self.batch is None:
+                self._rebuild()
+            # advance everyone by a chunk, or less so that the first request
+            # to finish ends exactly at its step count
+            k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
+            rc, stats = self.batch.run_status(k)
+            if rc not in (mprk.OK, mprk.ENONFINITE):
+                raise mprk.MprkError(rc, "mprk_batch_run")
+            for a in self.active:
+                a.done += k
+            # retire finished requests, and requests whose state went bad
+            keep = []
+            now = self.clock() - t0
+            for a, st in zip(self.active, stats):
+                if a.done >= a.req.steps or st["status"]:
+                    results.append(Result(a.req.rid, a.ql.cpu().numpy(), a.qu.cpu().numpy(), a.dt,
+                                          a.done, a.req.arrival, a.admitted, now, st["status"]))
+                    self.used -= a.bytes
+                else:
+                    keep.append(a)
+            if len(keep) != len(self.active):
+                self.active = keep
+                self.dirty = True
+            self.log.append((now, len(self.active), self.used))
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+        return results
+
+
+def summarize(results: List[Result], cell_stages: dict, makespan: float) -> dict:
+    """p50 / p99 latency and aggregate cell-stage updates/s of a served run."""
+    lat = np.array([r.latency for r in results])
+    total = sum(cell_stages[r.rid] for r in results)
+    return {
+        "requests": len(results),
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean())},
+        "makespan_s": makespan,
+        "cell_stage_updates_per_s": total / makespan if makespan > 0 else 0.0,
+        "bad": int(sum(r.status for r in results)),
+    }

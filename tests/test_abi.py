@@ -205,3 +205,18 @@ def test_batch_adaptive_arguments_checked():
     lib = mprk.load()
     assert lib.mprk_batch_set_adaptive(None, 0.5, 0.25) == mprk.EINVAL
     assert lib.mprk_batch_get_dt(None, 0, None) == mprk.EINVAL
+
+
+def test_serving_footprint_and_budget_check():
+    pytest.importorskip("torch")
+    from paper_2202_11890_amd import serving
+
+    w = inputs.small()
+    cfg = mprk.config_of_workload(w)
+    state = 8 * 4 * w.nx * (w.nz_lower + w.nz_upper)
+    fp = serving.footprint(cfg)
+    assert fp > state
+    ql, qu = inputs.initial_state(w)
+    srv = serving.Server("cpu", fp - 1)
+    with pytest.raises(ValueError):
+        srv.run([serving.Request(0, cfg, ql, qu, 5)])
