@@ -190,3 +190,148 @@ def uniform_state(w: Workload, rho: float, u: float, wv: float, p: float):
         q[3] = p / (g - 1) + 0.5 * rho * (u * u + wv * wv)
         res.append(q)
     return res[0], res[1]
+
+
+# ---- 3D (two stacked domains, x and y periodic) -------------------------------
+@dataclass(frozen=True)
+class Workload3:
+    name: str
+    nx: int
+    ny: int
+    nz_lower: int
+    nz_upper: int
+    lx: float = 10.0
+    ly: float = 10.0
+    lz_lower: float = 1.25      # fast domain below: dz_lower = dz_upper / 4 at equal nz
+    lz_upper: float = 5.0
+    fast_is_lower: bool = True
+    n_buffer: int = 5
+    base: int = 3
+    m: int = 4
+    steps: int = 200
+    gamma: float = 1.4
+    prandtl: float = 0.72
+    mu_lower: float = 1e-3
+    mu_upper: float = 1e-3
+    gravity: float = 0.0
+    t_lower: float = 1.0
+    t_upper: float = 1.0
+    amplitude: float = 1e-3
+    kmax: int = 4
+    seed: int = 3
+    cfl: float = 0.5
+    dnum: float = 0.25
+
+    @property
+    def dx(self) -> float:
+        return self.lx / self.nx
+
+    @property
+    def dy(self) -> float:
+        return self.ly / self.ny
+
+    @property
+    def dz_lower(self) -> float:
+        return self.lz_lower / self.nz_lower
+
+    @property
+    def dz_upper(self) -> float:
+        return self.lz_upper / self.nz_upper
+
+    def with_(self, **kw) -> "Workload3":
+        return replace(self, **kw)
+
+
+def large3d() -> Workload3:
+    """256 x 256 x 128 cells per domain, slow domain 5 high above a fast domain
+    1.25 high (dz_fast = dz_slow / 4), SSP-RK3 base, m = 4, 200 slow steps."""
+    return Workload3("two-domain 3D CNS 256x256x128 x2, MPRK3 m=4", nx=256, ny=256, nz_lower=128,
+                     nz_upper=128)
+
+
+def small3d() -> Workload3:
+    """A 3D case the oracle finishes in seconds: 24 x 20 x 12 below, x 10 above."""
+    return Workload3("two-domain 3D CNS 24x20x(12+10)", nx=24, ny=20, nz_lower=12, nz_upper=10,
+                     lz_lower=1.25 * 12 / 10, lz_upper=5.0, m=2, n_buffer=5, steps=10,
+                     amplitude=2e-2, seed=5)
+
+
+def initial_state3(w: Workload3):
+    """Uniform background (rho = 1/T, p = 1/gamma, at rest) plus random-phase
+    velocity perturbations: each of u, v, w is a sum of cos(kx x + ky y + phase)
+    over integer wavenumbers 1 <= |k| <= kmax (k in units of 2 pi / L), seeded
+    phases, scaled so the largest |component| is the amplitude (times the
+    local sound speed); w is multiplied by sin(pi zeta), zeta the height within
+    its domain, so it vanishes at the walls and at the interface."""
+    rng = np.random.default_rng(w.seed)
+    ks = [(a, b) for a in range(-w.kmax, w.kmax + 1) for b in range(-w.kmax, w.kmax + 1)
+          if 0 < a * a + b * b <= w.kmax * w.kmax]
+    x = -w.lx / 2 + (np.arange(w.nx) + 0.5) * w.dx
+    y = -w.ly / 2 + (np.arange(w.ny) + 0.5) * w.dy
+    X, Y = np.meshgrid(x, y)
+    fields = []
+    for _ in range(3):
+        ph = rng.uniform(0, 2 * np.pi, len(ks))
+        f = np.zeros_like(X)
+        for (a, b), p in zip(ks, ph):
+            f += np.cos(2 * np.pi * a * X / w.lx + 2 * np.pi * b * Y / w.ly + p)
+        fields.append(f / np.abs(f).max())
+    out = []
+    for lower in (True, False):
+        nz = w.nz_lower if lower else w.nz_upper
+        lz = w.lz_lower if lower else w.lz_upper
+        T = w.t_lower if lower else w.t_upper
+        g = w.gamma
+        p0 = 1.0 / g
+        rho = g * p0 / T
+        a = np.sqrt(T)
+        zeta = (np.arange(nz) + 0.5) / nz
+        q = np.zeros((5, nz, w.ny, w.nx))
+        u = w.amplitude * a * fields[0][None]
+        v = w.amplitude * a * fields[1][None]
+        ww = w.amplitude * a * fields[2][None] * np.sin(np.pi * zeta)[:, None, None]
+        u = np.broadcast_to(u, (nz, w.ny, w.nx))
+        v = np.broadcast_to(v, (nz, w.ny, w.nx))
+        q[0] = rho
+        q[1] = rho * u
+        q[2] = rho * v
+        q[3] = rho * ww
+        q[4] = p0 / (g - 1.0) + 0.5 * rho * (u * u + v * v + ww * ww)
+        out.append(q)
+    return out[0], out[1]
+
+
+def random_state3(w: Workload3, seed: int, amp: float = 0.05):
+    """Random physical 3D states: rho, T within +-amp of the background,
+    |u|, |v|, |w| <= amp a."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for lower in (True, False):
+        nz = w.nz_lower if lower else w.nz_upper
+        T0 = w.t_lower if lower else w.t_upper
+        g = w.gamma
+        shp = (nz, w.ny, w.nx)
+        rho = (1.0 / T0) * (1 + amp * rng.uniform(-1, 1, shp))
+        T = T0 * (1 + amp * rng.uniform(-1, 1, shp))
+        a = np.sqrt(T)
+        vel = [amp * a * rng.uniform(-1, 1, shp) for _ in range(3)]
+        q = np.zeros((5,) + shp)
+        q[0] = rho
+        for c in range(3):
+            q[1 + c] = rho * vel[c]
+        q[4] = rho * T / g / (g - 1) + 0.5 * rho * sum(v * v for v in vel)
+        out.append(q)
+    return out[0], out[1]
+
+
+def uniform_state3(w: Workload3, rho: float, u: float, v: float, wv: float, p: float):
+    out = []
+    for nz in (w.nz_lower, w.nz_upper):
+        q = np.zeros((5, nz, w.ny, w.nx))
+        q[0] = rho
+        q[1] = rho * u
+        q[2] = rho * v
+        q[3] = rho * wv
+        q[4] = p / (w.gamma - 1) + 0.5 * rho * (u * u + v * v + wv * wv)
+        out.append(q)
+    return out[0], out[1]
