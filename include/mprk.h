@@ -14,7 +14,8 @@
  *   the remaining slow rows.  R is the cell-centred second-order finite-volume
  *   RHS of Section 2.1 and Appendix B (local Lax-Friedrichs inviscid flux with
  *   a Roe-average wave speed, common-value viscous flux, bulk-coefficient
- *   coupling at Gamma, eq. bulk-flux), restricted to the x-z plane.
+ *   coupling at Gamma, eq. bulk-flux), in the x-z plane (dim 2) or in three
+ *   dimensions (dim 3, Appendix B as printed: x and y periodic).
  *   Time integration is the MPRK method of eq. (MRK2) with the stage
  *   schedule of Algorithm 1: the fast domain takes m substeps of dt/m, the
  *   buffer restarts from q^B_n at each substep with the full step and is
@@ -22,11 +23,14 @@
  *   reused at every substep.
  *
  * Data layout (device memory, caller-owned)
- *   q_lower, q_upper: float64 [4][nz][nx], x fastest, row 0 at the bottom,
- *   components (rho, rho u, rho w, rho E), nondimensional (Appendix A).
- *   Gamma lies between q_lower row nz_lower-1 and q_upper row 0.  x is
- *   periodic; the bottom of the lower domain and the top of the upper domain
- *   are slip adiabatic walls.
+ *   dim 2: q_lower, q_upper are float64 [4][nz][nx], x fastest, row 0 at the
+ *   bottom, components (rho, rho u, rho w, rho E).
+ *   dim 3: float64 [5][nz][ny][nx], components (rho, rho u, rho v, rho w,
+ *   rho E), x fastest, then y, then z (plane 0 at the bottom).
+ *   Nondimensional (Appendix A).  Gamma lies between the top row (plane) of
+ *   q_lower and the bottom one of q_upper.  x (and y) are periodic; the bottom
+ *   of the lower domain and the top of the upper domain are slip adiabatic
+ *   walls.
  *
  * Ownership and threading
  *   State, workspace and stream belong to the caller; the library never calls
@@ -51,7 +55,7 @@
 extern "C" {
 #endif
 
-#define MPRK_ABI_VERSION 1
+#define MPRK_ABI_VERSION 2
 
 enum mprk_status {
     MPRK_OK = 0,
@@ -98,8 +102,9 @@ enum mprk_region {
 
 typedef struct mprk_config {
     int32_t abi_version;    /* must be MPRK_ABI_VERSION                              */
-    int32_t dim;            /* 2 (x-z plane); 3 is reserved                          */
-    int32_t nx, ny;         /* cells in x (periodic); ny must be 1 when dim == 2     */
+    int32_t dim;            /* 2 (x-z plane) or 3 (x-y-z)                            */
+    int32_t nx, ny;         /* cells in x and y (periodic); ny must be 1 when dim == 2,
+                               >= 4 when dim == 3                                     */
     int32_t nz_lower;       /* rows of the lower domain                              */
     int32_t nz_upper;       /* rows of the upper domain                              */
     double dx, dy;          /* cell sizes in x (and y); dy is ignored in 2D          */
@@ -121,8 +126,9 @@ typedef struct mprk_config {
 } mprk_config;
 
 typedef struct mprk_stats {
-    double totals_lower[4]; /* sum of q |K| per component, lower domain (Sec. 5.1)    */
-    double totals_upper[4]; /* same, upper domain                                     */
+    double totals_lower[5]; /* sum of q |K| per component, lower domain (Sec. 5.1);
+                               2D: (rho, rho u, rho w, rho E, 0)                      */
+    double totals_upper[5]; /* same, upper domain                                     */
     double lambda_lower;    /* max over cells of sum_d (|u_d| + a) / d_d              */
     double lambda_upper;
     double courant_lower;   /* max over cells and directions of (|u_d| + a) / d_d     */
@@ -198,7 +204,9 @@ int mprk_stable_dt(const mprk_config* cfg, const mprk_stats* st, double cr, doub
  * computed by the same code from the same inputs.  The persistent mode needs
  * cooperative launch support (else mprk_run returns MPRK_EUNSUPPORTED); its
  * waits are bounded (2 s), so a run can end with MPRK_ETIMEOUT but never
- * hangs.  Kernel timing (mprk_profile_*) covers the launch mode only. */
+ * hangs.  Kernel timing (mprk_profile_*) covers the launch mode only.  3D
+ * contexts support MPRK_EXEC_LAUNCH and MPRK_EXEC_GRAPH (MPRK_EXEC_PERSISTENT:
+ * MPRK_EUNSUPPORTED). */
 int mprk_set_exec(mprk_ctx* ctx, int mode);
 
 /* Longest time (seconds, default 2) a tile of a persistent run waits for a
@@ -206,7 +214,8 @@ int mprk_set_exec(mprk_ctx* ctx, int mode);
 int mprk_set_wait_limit(mprk_ctx* ctx, double seconds);
 
 /* Tile shape of later launches (an mprk_tile value; default MPRK_TILE_32X16).
- * Results are bit-identical for every shape. */
+ * Results are bit-identical for every shape.  3D contexts have one tile shape
+ * per flux precision (other values: MPRK_EUNSUPPORTED). */
 int mprk_set_tile(mprk_ctx* ctx, int shape);
 
 /* Kernel timing aid.  While enabled, every stage launch is bracketed by a
@@ -235,7 +244,8 @@ const char* mprk_strerror(int code);
  * empty.  A member's arithmetic is exactly that of a single context with the
  * same configuration and step: results are bit-identical whatever else is in
  * the batch, and in every execution mode and tile shape.
- * All members must share flux_bits.  States are caller-owned device arrays
+ * Members are 2D problems (dim 3: MPRK_EUNSUPPORTED) and must share
+ * flux_bits.  States are caller-owned device arrays
  * (layout as above) that must not overlap. */
 typedef struct mprk_member {
     mprk_config cfg;

@@ -1,0 +1,85 @@
+// mprk_device.h -- device helpers shared by the 2D and 3D stage kernels of
+// the MPRK library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mprk {
+namespace {
+
+__device__ __forceinline__ int wrapx(int c, int nx)
+{
+    int r = c % nx;
+    return r < 0 ? r + nx : r;
+}
+
+// 1/sqrt(x) for positive normal x: hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2 (quadratic convergence; a few ulp).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+
+// 1/x for positive normal x: hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// Reciprocal, square root and reciprocal square root of positive normal
+// arguments in the flux type.  FP64: hardware estimates refined by Newton
+// steps (a few ulp).  FP32: the hardware instructions (1 ulp).  No scaling
+// for subnormals, zero or infinity, which a physical state never produces; a
+// non-physical one yields NaN, which the device status check reports.
+//
+// ws_sqrt and ws_rcp serve only the wave-speed estimate lambda of the LLF
+// flux (sound speeds and Roe weights), which scales the dissipation term and
+// does not enter the physical flux: in FP64 they take one Newton step from
+// the hardware estimate, whose relative error is then the square of the
+// estimate's (about 1e-14 and below).
+template <class FT> struct Fm;
+template <> struct Fm<double> {
+    static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return rsqrt_nr(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return x * rsqrt_nr(x); }
+    static __device__ __forceinline__ double ws_sqrt(double x)
+    {
+        // s = x y ~ sqrt(x); s + (y/2)(x - s^2)
+        const double y = __builtin_amdgcn_rsq(x);
+        const double s = x * y;
+        return fma(0.5 * y, fma(-s, s, x), s);
+    }
+    static __device__ __forceinline__ double ws_rcp(double x)
+    {
+        const double y = __builtin_amdgcn_rcp(x);
+        return fma(y, fma(-x, y, 1.0), y);
+    }
+};
+template <> struct Fm<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float ws_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float ws_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block j to XCD j % 8).
+// Give each XCD a contiguous range of the n tiles so that neighbouring tiles,
+// which share halo rows and columns, meet in the same L2.
+__device__ __forceinline__ int xcd_contiguous(int j, int n)
+{
+    constexpr int NXCD = 8;
+    const int x = j % NXCD, i = j / NXCD;
+    const int per = n / NXCD, rem = n % NXCD;
+    return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+}  // namespace
+}  // namespace mprk

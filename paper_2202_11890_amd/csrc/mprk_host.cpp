@@ -48,9 +48,16 @@ int shu_osher(int base, double* alpha)
 
 int tiles_of(int n, int t) { return (n + t - 1) / t; }
 
-// Fixed tiles of both domains for a tile shape.
+int nv_of(const mprk_config& c) { return c.dim == 3 ? NV3 : NV; }
+
+// Fixed tiles of both domains for a tile shape (3D: the 3D kernel's tile).
 int member_tiles(const mprk_config& c, int shape)
 {
+    if (c.dim == 3) {
+        const TileDims3 d = tile3_dims(c.flux_bits == 32);
+        return tiles_of(c.nx, d.tx) * tiles_of(c.ny, d.ty) *
+               (tiles_of(c.nz_lower, d.tz) + tiles_of(c.nz_upper, d.tz));
+    }
     const TileDims d = tile_dims(shape);
     return tiles_of(c.nx, d.tx) * (tiles_of(c.nz_lower, d.tz) + tiles_of(c.nz_upper, d.tz));
 }
@@ -81,8 +88,9 @@ bool core_layout(const mprk_config* c, CoreLayout* L)
     int s = shu_osher(c->base_rk, al);
     if (s < 0) return false;
     L->s = s;
-    L->n_lo = (size_t)NV * c->nz_lower * c->nx;
-    L->n_up = (size_t)NV * c->nz_upper * c->nx;
+    const size_t nv = nv_of(*c), row = (size_t)c->nx * (c->dim == 3 ? c->ny : 1);
+    L->n_lo = nv * c->nz_lower * row;
+    L->n_up = nv * c->nz_upper * row;
     size_t off = 0;
     for (int j = 0; j < 3; ++j) { L->off_stage_lo[j] = L->off_stage_up[j] = 0; L->off_ret[j] = 0; }
     for (int j = 0; j < s - 1; ++j) {
@@ -94,10 +102,10 @@ bool core_layout(const mprk_config* c, CoreLayout* L)
     const bool multi = c->m > 1;
     for (int j = 0; j < s; ++j) {
         L->off_ret[j] = off;
-        if (multi) off += round_up((size_t)NV * 2 * c->nx * sizeof(double));
+        if (multi) off += round_up(nv * 2 * row * sizeof(double));
     }
     L->off_acc = off;
-    if (multi) off += round_up((size_t)NV * c->n_buffer * c->nx * sizeof(double));
+    if (multi) off += round_up(nv * c->n_buffer * row * sizeof(double));
     L->off_partial = off;
     off += round_up((size_t)2 * RED_BLOCKS * RED_FIELDS * sizeof(double));
     L->off_final = off;
@@ -180,6 +188,9 @@ StageArgs base_args(const Member& mb)
     StageArgs a;
     std::memset(&a, 0, sizeof a);
     a.nx = g.nx;
+    a.ny = g.dim == 3 ? g.ny : 1;
+    a.dy = g.dim == 3 ? g.dy : 0.0;
+    a.inv_dy = g.dim == 3 ? 1.0 / g.dy : 0.0;
     a.dx = g.dx;
     a.inv_dx = 1.0 / g.dx;
     a.gamma = g.gamma;
@@ -209,14 +220,27 @@ StageArgs base_args(const Member& mb)
     return a;
 }
 
-void set_rows(DomainArgs& D, int nx, int lo, int hi, int shape)
+// Tiles of a launch over rows (z-planes) [lo, hi): fixed tiles, z aligned at
+// multiples of the tile height.  shape < 0 selects the 3D kernel's tile.
+void set_rows(DomainArgs& D, const mprk_config& g, int lo, int hi, int shape)
 {
-    const TileDims t = tile_dims(shape);
+    int tx, ty = 1, tz;
+    if (g.dim == 3) {
+        const TileDims3 t = tile3_dims(g.flux_bits == 32);
+        tx = t.tx;
+        ty = t.ty;
+        tz = t.tz;
+    } else {
+        const TileDims t = tile_dims(shape);
+        tx = t.tx;
+        tz = t.tz;
+    }
     D.row_lo = lo;
     D.row_hi = hi;
-    D.tiles_x = tiles_of(nx, t.tx);
-    D.tiles_z = hi > lo ? (hi - 1) / t.tz - lo / t.tz + 1 : 0;   // fixed tiles meeting [lo, hi)
-    D.ntiles = D.tiles_x * D.tiles_z;
+    D.tiles_x = tiles_of(g.nx, tx);
+    D.tiles_y = g.dim == 3 ? tiles_of(g.ny, ty) : 1;
+    D.tiles_z = hi > lo ? (hi - 1) / tz - lo / tz + 1 : 0;   // fixed tiles meeting [lo, hi)
+    D.ntiles = D.tiles_x * D.tiles_y * D.tiles_z;
 }
 
 // Block count and block order of a stage record: launches that cover only
@@ -262,7 +286,7 @@ StageArgs stage_args(const Member& mb, double dt, int k, int j, int shape)
     DF.out = last ? qF : mb.stage(F, j);
     DF.main = combine(al, hF, MODE_STAGE);
     DF.buf = DF.main;
-    set_rows(DF, g.nx, 0, nzF, shape);
+    set_rows(DF, g, 0, nzF, shape);
 
     // Slow domain.
     DomainArgs& DS = a.d[S];
@@ -273,7 +297,7 @@ StageArgs stage_args(const Member& mb, double dt, int k, int j, int shape)
         // Single rate: buffer and slow rows are the same base step.
         DS.main = combine(al, dt, MODE_STAGE);
         DS.buf = DS.main;
-        set_rows(DS, g.nx, 0, nzS, shape);
+        set_rows(DS, g, 0, nzS, shape);
     } else {
         DS.b_lo = mb.b_lo;
         DS.b_hi = mb.b_hi;
@@ -289,11 +313,11 @@ StageArgs stage_args(const Member& mb, double dt, int k, int j, int shape)
             // Slow rows: one base step; keep the two rows next to the buffer of
             // each stage value for the later substeps.
             DS.ret_out = mb.ret(j - 1);
-            set_rows(DS, g.nx, 0, nzS, shape);
+            set_rows(DS, g, 0, nzS, shape);
         } else {
             DS.use_ret = 1;
             DS.ret_in = mb.ret(j - 1);
-            set_rows(DS, g.nx, mb.b_lo, mb.b_hi, shape);
+            set_rows(DS, g, mb.b_lo, mb.b_hi, shape);
         }
     }
     finish_record(mb, a);
@@ -333,12 +357,16 @@ ReduceArgs member_reduce_args(const Member& mb, double* final_)
     r.nz[0] = g.nz_lower;
     r.nz[1] = g.nz_upper;
     r.nx = g.nx;
+    r.ny = g.dim == 3 ? g.ny : 1;
+    r.nv = nv_of(g);
     r.inv_dx = 1.0 / g.dx;
+    r.inv_dy = g.dim == 3 ? 1.0 / g.dy : 0.0;
     r.inv_dz[0] = 1.0 / g.dz_lower;
     r.inv_dz[1] = 1.0 / g.dz_upper;
     const double coef = std::max(4.0 / 3.0, g.gamma / g.prandtl);
-    r.visc_coef[0] = coef * g.mu_lower * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_lower * g.dz_lower));
-    r.visc_coef[1] = coef * g.mu_upper * (1.0 / (g.dx * g.dx) + 1.0 / (g.dz_upper * g.dz_upper));
+    const double hy = g.dim == 3 ? 1.0 / (g.dy * g.dy) : 0.0;
+    r.visc_coef[0] = coef * g.mu_lower * (1.0 / (g.dx * g.dx) + hy + 1.0 / (g.dz_lower * g.dz_lower));
+    r.visc_coef[1] = coef * g.mu_upper * (1.0 / (g.dx * g.dx) + hy + 1.0 / (g.dz_upper * g.dz_upper));
     r.gamma = g.gamma;
     r.gm1 = g.gamma - 1.0;
     r.partial = (double*)(mb.ws + mb.lay.off_partial);
@@ -363,16 +391,18 @@ int member_stats(const Member& mb, const double* host_final, int64_t steps, mprk
     const mprk_config& g = mb.cfg;
     mprk_stats st;
     std::memset(&st, 0, sizeof st);
-    const double area[2] = {g.dx * g.dz_lower, g.dx * g.dz_upper};
+    const double dy = g.dim == 3 ? g.dy : 1.0;
+    const double cellv[2] = {g.dx * dy * g.dz_lower, g.dx * dy * g.dz_upper};
+    const int nv = nv_of(g);
     int bad = 0;
     for (int d = 0; d < 2; ++d) {
         const double* f = host_final + d * RED_FIELDS;
         double* tot = d == 0 ? st.totals_lower : st.totals_upper;
-        for (int v = 0; v < NV; ++v) tot[v] = (f[v] + f[NV + v]) * area[d];
-        (d == 0 ? st.lambda_lower : st.lambda_upper) = f[8];
-        (d == 0 ? st.courant_lower : st.courant_upper) = f[9];
-        (d == 0 ? st.visc_lower : st.visc_upper) = f[10];
-        if (f[11] != 0.0) bad = 1;
+        for (int v = 0; v < nv; ++v) tot[v] = (f[v] + f[5 + v]) * cellv[d];
+        (d == 0 ? st.lambda_lower : st.lambda_upper) = f[10];
+        (d == 0 ? st.courant_lower : st.courant_upper) = f[11];
+        (d == 0 ? st.visc_lower : st.visc_upper) = f[12];
+        if (f[13] != 0.0) bad = 1;
     }
     st.steps_done = steps;
     st.status = bad;
@@ -542,9 +572,17 @@ namespace {
 
 // ---- single context ------------------------------------------------------
 
+hipError_t launch_any(const mprk_ctx* c, const StageArgs& a)
+{
+    if (c->mb.cfg.dim == 3) return launch_stage3(a, c->stream);
+    return launch_stage(a, c->shape, c->stream);
+}
+
+hipError_t launch_any(const mprk_ctx* c, const StageArgs& a);
+
 int launch(mprk_ctx* c, const StageArgs& a)
 {
-    if (!c->prof_on) return launch_stage(a, c->shape, c->stream) == hipSuccess ? MPRK_OK : MPRK_EHIP;
+    if (!c->prof_on) return launch_any(c, a) == hipSuccess ? MPRK_OK : MPRK_EHIP;
     if (2 * c->prof_used + 2 > c->prof_ev.size()) {
         for (int i = 0; i < 2; ++i) {
             hipEvent_t ev;
@@ -554,7 +592,7 @@ int launch(mprk_ctx* c, const StageArgs& a)
     }
     hipEvent_t e0 = c->prof_ev[2 * c->prof_used], e1 = c->prof_ev[2 * c->prof_used + 1];
     if (hipEventRecord(e0, c->stream) != hipSuccess) return MPRK_EHIP;
-    if (launch_stage(a, c->shape, c->stream) != hipSuccess) return MPRK_EHIP;
+    if (launch_any(c, a) != hipSuccess) return MPRK_EHIP;
     if (hipEventRecord(e1, c->stream) != hipSuccess) return MPRK_EHIP;
     c->prof_used += 1;
     return MPRK_OK;
@@ -583,7 +621,8 @@ int ctx_graph(mprk_ctx* c, double dt)
         for (int j = 1; j <= s; ++j) c->g_args.push_back(stage_args(c->mb, dt, k, j, c->shape));
     c->g_ptrs.resize(ms);
     if (!c->graph.begin()) return MPRK_EHIP;
-    const KernelRef kr = stage_kernel_ref(c->mb.cfg.flux_bits == 32, c->shape);
+    const KernelRef kr = c->mb.cfg.dim == 3 ? stage3_kernel_ref(c->mb.cfg.flux_bits == 32)
+                                            : stage_kernel_ref(c->mb.cfg.flux_bits == 32, c->shape);
     hipGraphNode_t prev = nullptr;
     for (int i = 0; i < ms; ++i) {
         if (c->g_args[i].nblocks <= 0) continue;
@@ -605,6 +644,7 @@ int ctx_graph(mprk_ctx* c, double dt)
 // One persistent launch running nsteps slow steps.
 int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
 {
+    if (c->mb.cfg.dim == 3) return MPRK_EUNSUPPORTED;
     const mprk_config& g = c->mb.cfg;
     const int ms = c->mb.ms();
     char* ws = c->mb.ws;
@@ -716,6 +756,10 @@ int batch_check(const mprk_member* mem, int32_t n, char* msg, size_t len)
         if (rc != MPRK_OK) {
             set_msg(msg, len, "member %d: %s", i, m2);
             return rc;
+        }
+        if (mem[i].cfg.dim != 2) {
+            set_msg(msg, len, "member %d: batches hold 2D problems", i);
+            return MPRK_EUNSUPPORTED;
         }
         if (mem[i].cfg.flux_bits != mem[0].cfg.flux_bits) {
             set_msg(msg, len, "member %d: every member must use the same flux_bits", i);
@@ -1030,14 +1074,18 @@ int mprk_validate(const mprk_config* c, char* msg, size_t len)
         set_msg(msg, len, "abi_version %d, library %d", c->abi_version, MPRK_ABI_VERSION);
         return MPRK_EINVAL;
     }
-    if (c->dim == 3) { set_msg(msg, len, "dim 3 is not implemented"); return MPRK_EUNSUPPORTED; }
-    if (c->dim != 2) { set_msg(msg, len, "dim must be 2"); return MPRK_EINVAL; }
-    if (c->ny != 1) { set_msg(msg, len, "ny must be 1 in 2D"); return MPRK_EINVAL; }
+    if (c->dim != 2 && c->dim != 3) { set_msg(msg, len, "dim must be 2 or 3"); return MPRK_EINVAL; }
+    if (c->dim == 2 && c->ny != 1) { set_msg(msg, len, "ny must be 1 in 2D"); return MPRK_EINVAL; }
+    if (c->dim == 3 && (c->ny < 4 || !(c->dy > 0) || !std::isfinite(c->dy))) {
+        set_msg(msg, len, "3D needs ny >= 4 and a positive finite dy");
+        return MPRK_EINVAL;
+    }
     if (c->nx < 4 || c->nz_lower < 3 || c->nz_upper < 3) {
         set_msg(msg, len, "need nx >= 4 and nz >= 3 per domain");
         return MPRK_EINVAL;
     }
-    if ((long long)c->nx * std::max(c->nz_lower, c->nz_upper) > (1LL << 28)) {
+    const long long ny_ = c->dim == 3 ? c->ny : 1;
+    if ((long long)c->nx * ny_ * std::max(c->nz_lower, c->nz_upper) > (1LL << 28)) {
         set_msg(msg, len, "domain larger than 2^28 cells");
         return MPRK_EINVAL;
     }
@@ -1185,7 +1233,7 @@ int mprk_rhs(mprk_ctx* c, const double* q_lower, const double* q_upper, double* 
                 else { lo = 0; hi = mb.b_lo; }
             }
         }
-        set_rows(D, g.nx, lo, hi, c->shape);
+        set_rows(D, g, lo, hi, c->shape);
     }
     finish_record(mb, a);
     return launch(c, a);
@@ -1194,6 +1242,7 @@ int mprk_rhs(mprk_ctx* c, const double* q_lower, const double* q_upper, double* 
 int mprk_set_exec(mprk_ctx* c, int mode)
 {
     if (!c || !valid_mode(mode)) return MPRK_EINVAL;
+    if (c->mb.cfg.dim == 3 && mode == MPRK_EXEC_PERSISTENT) return MPRK_EUNSUPPORTED;
     c->exec = mode;
     return MPRK_OK;
 }
@@ -1201,6 +1250,7 @@ int mprk_set_exec(mprk_ctx* c, int mode)
 int mprk_set_tile(mprk_ctx* c, int shape)
 {
     if (!c || shape < 0 || shape >= MPRK_TILE_SHAPES) return MPRK_EINVAL;
+    if (c->mb.cfg.dim == 3 && shape != MPRK_TILE_32X16) return MPRK_EUNSUPPORTED;
     c->shape = shape;
     return MPRK_OK;
 }

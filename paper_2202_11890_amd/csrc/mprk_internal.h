@@ -7,7 +7,8 @@
 
 namespace mprk {
 
-constexpr int NV = 4;          // (rho, rho u, rho w, rho E)
+constexpr int NV = 4;          // 2D: (rho, rho u, rho w, rho E)
+constexpr int NV3 = 5;         // 3D: (rho, rho u, rho v, rho w, rho E)
 
 // Stage tile shapes: TX columns x TZ rows of cells per workgroup of
 // TX*TZ/2 threads; each thread owns a vertical pair of cells.  The conserved
@@ -24,6 +25,10 @@ enum TileShape : int32_t {
 
 struct TileDims {
     int tx, tz, nt;
+};
+
+struct TileDims3 {
+    int tx, ty, tz, nt;
 };
 
 inline TileDims tile_dims(int shape)
@@ -54,8 +59,9 @@ struct Combine {
     int32_t pad;
 };
 
+// Domain arrays are [nv][nz][ny][nx] (ny = 1 in 2D); a "row" is a z-plane.
 struct DomainArgs {
-    const double* qin;     // stage value read by the stencil [NV][nz][nx]
+    const double* qin;     // stage value read by the stencil [nv][nz][ny][nx]
     const double* base;    // substep base U (pointwise)
     double* out;           // destination of MODE_RHS / STAGE / ACC_FINAL
     double* acc;           // buffer accumulator [NV][b_hi-b_lo][nx]
@@ -71,6 +77,7 @@ struct DomainArgs {
     int32_t gamma_top;       // 1: the interface is above the top row
     int32_t gamma_bot;       // 1: the interface is below row 0
     int32_t tiles_x, tiles_z, ntiles;
+    int32_t tiles_y;         // 3D only (1 in 2D)
     double dz, inv_dz;
     double mu, kappa;
     Combine main;            // rows outside [b_lo, b_hi)
@@ -80,6 +87,8 @@ struct DomainArgs {
 struct StageArgs {
     DomainArgs d[2];         // 0 = lower, 1 = upper
     int32_t nx;
+    int32_t ny;              // 1 in 2D
+    double dy, inv_dy;       // 3D only
     int32_t nblocks;         // d[0].ntiles + d[1].ntiles
     int32_t first;           // domain whose tiles take the first blocks
     int32_t flux32;          // 1: face fluxes in FP32 (state, stage sums, interface flux FP64)
@@ -93,14 +102,16 @@ struct StageArgs {
 // Reductions: per-domain fields.
 constexpr int RED_BLOCKS = 256;   // partial blocks per domain
 constexpr int RED_THREADS = 256;
-constexpr int RED_FIELDS = 12;    // sum[4], comp[4], lambda, courant, visc, bad
+constexpr int RED_FIELDS = 14;    // sum[5], comp[5], lambda, courant, visc, bad
 
 struct ReduceArgs {
     const double* q[2];
     int32_t nz[2];
-    int32_t nx;
-    double inv_dx, inv_dz[2];
-    double visc_coef[2];     // max(4/3, gamma/Pr) * mu_d * (1/dx^2 + 1/dz_d^2)
+    int32_t nx, ny;          // ny = 1 in 2D
+    int32_t nv;              // 4 (2D) or 5 (3D)
+    int32_t pad;
+    double inv_dx, inv_dy, inv_dz[2];
+    double visc_coef[2];     // max(4/3, gamma/Pr) * mu_d * sum over directions of 1/h^2
     double gamma, gm1;
     double* partial;         // [2][RED_BLOCKS][RED_FIELDS]
     double* final_;          // [2][RED_FIELDS]
@@ -165,6 +176,10 @@ hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int sh
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
 int persistent_blocks_per_cu(bool flux32, int shape);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+// 3D stage kernel (one tile shape per flux type).
+hipError_t launch_stage3(const StageArgs& a, hipStream_t s);
+KernelRef stage3_kernel_ref(bool flux32);
+TileDims3 tile3_dims(bool flux32);
 hipError_t launch_reduce_batch(const ReduceArgs* tab, int n, hipStream_t s);
 
 }  // namespace mprk

@@ -18,6 +18,7 @@
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
 // stability measures and the physical-state flag.
 #include "mprk_internal.h"
+#include "mprk_device.h"
 
 namespace mprk {
 
@@ -50,69 +51,6 @@ struct Shape {
     constexpr int TX = S::TX, TZ = S::TZ, NT = S::NT, HX = S::HX, HZ = S::HZ;            \
     constexpr int PX = S::PX, PZ = S::PZ;                                                \
     (void)TX; (void)TZ; (void)NT; (void)HX; (void)HZ; (void)PX; (void)PZ
-
-__device__ __forceinline__ int wrapx(int c, int nx)
-{
-    int r = c % nx;
-    return r < 0 ? r + nx : r;
-}
-
-// 1/sqrt(x) for positive normal x: hardware estimate refined by two Newton
-// steps y <- y + y (1 - x y^2) / 2 (quadratic convergence; a few ulp).
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double r = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, r, y);
-    r = fma(-(x * y), y, 1.0);
-    return fma(0.5 * y, r, y);
-}
-
-// 1/x for positive normal x: hardware estimate refined by two Newton steps
-// y <- y + y (1 - x y).
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    y = fma(y, fma(-x, y, 1.0), y);
-    return fma(y, fma(-x, y, 1.0), y);
-}
-
-// Reciprocal, square root and reciprocal square root of positive normal
-// arguments in the flux type.  FP64: hardware estimates refined by Newton
-// steps (a few ulp).  FP32: the hardware instructions (1 ulp).  No scaling
-// for subnormals, zero or infinity, which a physical state never produces; a
-// non-physical one yields NaN, which the device status check reports.
-//
-// ws_sqrt and ws_rcp serve only the wave-speed estimate lambda of the LLF
-// flux (sound speeds and Roe weights), which scales the dissipation term and
-// does not enter the physical flux: in FP64 they take one Newton step from
-// the hardware estimate, whose relative error is then the square of the
-// estimate's (about 1e-14 and below).
-template <class FT> struct Fm;
-template <> struct Fm<double> {
-    static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }
-    static __device__ __forceinline__ double rsqrt(double x) { return rsqrt_nr(x); }
-    static __device__ __forceinline__ double sqrt(double x) { return x * rsqrt_nr(x); }
-    static __device__ __forceinline__ double ws_sqrt(double x)
-    {
-        // s = x y ~ sqrt(x); s + (y/2)(x - s^2)
-        const double y = __builtin_amdgcn_rsq(x);
-        const double s = x * y;
-        return fma(0.5 * y, fma(-s, s, x), s);
-    }
-    static __device__ __forceinline__ double ws_rcp(double x)
-    {
-        const double y = __builtin_amdgcn_rcp(x);
-        return fma(y, fma(-x, y, 1.0), y);
-    }
-};
-template <> struct Fm<float> {
-    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-    static __device__ __forceinline__ float ws_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-    static __device__ __forceinline__ float ws_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-};
 
 // Cell primitives u, w, T in the flux type (staged for the viscous fluxes).
 template <class FT>
@@ -535,17 +473,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     }
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block j to XCD j % 8).
-// Give each XCD a contiguous range of the n tiles so that neighbouring tiles,
-// which share halo rows and columns, meet in the same L2.
-__device__ __forceinline__ int xcd_contiguous(int j, int n)
-{
-    constexpr int NXCD = 8;
-    const int x = j % NXCD, i = j / NXCD;
-    const int per = n / NXCD, rem = n % NXCD;
-    return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
-}
-
 #ifndef MPRK_WAVES_PER_EU
 #define MPRK_WAVES_PER_EU 3
 #endif
@@ -693,8 +620,10 @@ __global__ void fill_i32(int32_t* p, int32_t v, int n)
 // ---------------------------------------------------------------------------
 // Reductions.
 // ---------------------------------------------------------------------------
+constexpr int RV = 5;        // components summed (2D uses the first 4)
+
 struct RedVal {
-    double s[NV], e[NV];     // compensated sums: value + error term
+    double s[RV], e[RV];     // compensated sums: value + error term
     double lam, cour, vis, bad;
 };
 
@@ -708,7 +637,7 @@ __device__ __forceinline__ void two_sum(double& s, double& e, double x)
 __device__ __forceinline__ void red_combine(RedVal& a, const RedVal& b)
 {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int v = 0; v < RV; ++v) {
         two_sum(a.s[v], a.e[v], b.s[v]);
         a.e[v] += b.e[v];
     }
@@ -718,18 +647,20 @@ __device__ __forceinline__ void red_combine(RedVal& a, const RedVal& b)
     a.bad = fmax(a.bad, b.bad);
 }
 
+// Field layout: sums [0, 5), compensation terms [5, 10), then lambda,
+// courant, visc, bad.
 __device__ __forceinline__ void red_store(double* p, const RedVal& a)
 {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { p[v] = a.s[v]; p[NV + v] = a.e[v]; }
-    p[8] = a.lam; p[9] = a.cour; p[10] = a.vis; p[11] = a.bad;
+    for (int v = 0; v < RV; ++v) { p[v] = a.s[v]; p[RV + v] = a.e[v]; }
+    p[10] = a.lam; p[11] = a.cour; p[12] = a.vis; p[13] = a.bad;
 }
 
 __device__ __forceinline__ void red_load(const double* p, RedVal& a)
 {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { a.s[v] = p[v]; a.e[v] = p[NV + v]; }
-    a.lam = p[8]; a.cour = p[9]; a.vis = p[10]; a.bad = p[11];
+    for (int v = 0; v < RV; ++v) { a.s[v] = p[v]; a.e[v] = p[RV + v]; }
+    a.lam = p[10]; a.cour = p[11]; a.vis = p[12]; a.bad = p[13];
 }
 
 // Fixed-shape tree over the block: the result does not depend on timing.
@@ -751,34 +682,44 @@ __device__ void block_tree(RedVal& mine, double* sh)
     red_load(sh, mine);
 }
 
+// Totals, stability measures and the bad-state flag of one domain (2D: the
+// components are (rho, rho u, rho w, rho E); 3D: (rho, rho u, rho v, rho w,
+// rho E)).
 __device__ __forceinline__ void reduce_partial_body(const ReduceArgs& A, int dom, int blk, double* sh)
 {
     const double* q = A.q[dom];
-    const int n = A.nz[dom] * A.nx;
+    const int nv = A.nv;
+    const bool three = nv == 5;
+    const int n = A.nz[dom] * A.ny * A.nx;
     const double inv_dz = A.inv_dz[dom], vc = A.visc_coef[dom];
     RedVal m;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { m.s[v] = 0.0; m.e[v] = 0.0; }
+    for (int v = 0; v < RV; ++v) { m.s[v] = 0.0; m.e[v] = 0.0; }
     m.lam = m.cour = m.vis = m.bad = 0.0;
     for (int i = blk * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
-        const double rho = q[i], mx = q[(size_t)n + i], mz = q[2 * (size_t)n + i],
-                     en = q[3 * (size_t)n + i];
-        two_sum(m.s[0], m.e[0], rho);
-        two_sum(m.s[1], m.e[1], mx);
-        two_sum(m.s[2], m.e[2], mz);
-        two_sum(m.s[3], m.e[3], en);
+        double c[RV];
+#pragma unroll
+        for (int v = 0; v < RV; ++v) c[v] = v < nv ? q[(size_t)v * n + i] : 0.0;
+#pragma unroll
+        for (int v = 0; v < RV; ++v) two_sum(m.s[v], m.e[v], c[v]);
+        const double rho = c[0];
+        const double mx = c[1], my = three ? c[2] : 0.0, mz = three ? c[3] : c[2];
+        const double en = three ? c[4] : c[3];
         const double ir = 1.0 / rho;
-        const double u = mx * ir, w = mz * ir;
-        const double p = A.gm1 * (en - 0.5 * (mx * u + mz * w));
-        const bool ok = (rho > 0.0) && (p > 0.0) && isfinite(mx) && isfinite(mz) && isfinite(en);
+        const double u = mx * ir, v = my * ir, w = mz * ir;
+        const double p = A.gm1 * (en - 0.5 * (mx * u + my * v + mz * w));
+        bool ok = (rho > 0.0) && (p > 0.0);
+#pragma unroll
+        for (int k = 0; k < RV; ++k) ok = ok && isfinite(c[k]);
         if (!ok) {
             m.bad = 1.0;
         } else {
             const double a = sqrt(A.gamma * p * ir);
             const double sx = (fabs(u) + a) * A.inv_dx;
+            const double sy = three ? (fabs(v) + a) * A.inv_dy : 0.0;
             const double sz = (fabs(w) + a) * inv_dz;
-            m.lam = fmax(m.lam, sx + sz);
-            m.cour = fmax(m.cour, fmax(sx, sz));
+            m.lam = fmax(m.lam, sx + sy + sz);
+            m.cour = fmax(m.cour, fmax(fmax(sx, sy), sz));
             m.vis = fmax(m.vis, vc * ir);
         }
     }

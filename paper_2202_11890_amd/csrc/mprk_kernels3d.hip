@@ -1,0 +1,536 @@
+// mprk_kernels3d.hip -- gfx950 stage kernel of the MPRK library in three
+// dimensions (Appendix B, eq. ns-fv-cartesian-3d: x and y periodic, the two
+// domains stacked in z and coupled through the rigid lid).
+//
+// Same structure as the 2D kernel: a workgroup owns a TX x TY x TZ tile of one
+// domain; each thread owns a vertical pair of cells.  The conserved state
+// (5 components, 2-cell halo) and the primitives u, v, w, T (1-cell halo) are
+// staged in LDS in the flux type; every face of the tile is evaluated once
+// (three per cell plus the left, front and bottom edge faces), exchanged
+// through LDS (aliasing the staged state), and each thread forms the
+// divergence and the stage combination of its cells in FP64.  The interface
+// viscous flux is computed per column in FP64 and added in the divergence.
+#include "mprk_internal.h"
+#include "mprk_device.h"
+
+namespace mprk {
+
+namespace {
+
+template <int X, int Y, int Z>
+struct Shape3 {
+    static constexpr int TX = X, TY = Y, TZ = Z, NT = X * Y * Z / 2;
+    static constexpr int HX = X + 4, HY = Y + 4, HZ = Z + 4;
+    static constexpr int PX = X + 2, PY = Y + 2, PZ = Z + 2;
+    static constexpr int QPL = HY * HX;                 // staged state: one z-plane
+    static constexpr int LDS_Q = NV3 * HZ * QPL;
+    static constexpr int PPL = PY * PX;
+    static constexpr int LDS_P = 4 * PZ * PPL;          // u, v, w, T
+    static constexpr int EXX = Z * Y * (X + 1), EXY = Z * (Y + 1) * X, EXZ = (Z + 1) * Y * X;
+    static constexpr int LDS_EX = NV3 * (EXX + EXY + EXZ);
+    static_assert(Z % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
+    static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
+    template <class FT>
+    static constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 3 * X * Y * 8; }
+};
+
+using T32 = Shape3<16, 8, 4>;     // FP32 fluxes: 256 threads, 55.7 KB
+using T64 = Shape3<8, 4, 4>;      // FP64 fluxes: 64 threads, 42.1 KB
+
+template <class FT> struct TileOf;
+template <> struct TileOf<float> { using S = T32; };
+template <> struct TileOf<double> { using S = T64; };
+
+template <class FT>
+struct Lds3 {
+    FT* q;        // [5][HZ][HY][HX]
+    FT* p;        // [4][PZ][PY][PX]
+    double* gf;   // [3][TY*TX]: interface flux (x-, y-momentum, energy) per column
+};
+
+template <class S>
+__device__ __forceinline__ int q3(int v, int z, int y, int x)
+{
+    return ((v * S::HZ + z + 2) * S::HY + y + 2) * S::HX + x + 2;
+}
+template <class S>
+__device__ __forceinline__ int p3(int f, int z, int y, int x)
+{
+    return ((f * S::PZ + z + 1) * S::PY + y + 1) * S::PX + x + 1;
+}
+
+enum : int { F3_INTERIOR = 0, F3_TOP = 1, F3_BOTTOM = 2 };
+
+template <class FT>
+__device__ __forceinline__ void prim3(const FT* c, FT gamma, FT gm1, FT& u, FT& v, FT& w, FT& T)
+{
+    const FT ir = Fm<FT>::rcp(c[0]);
+    u = c[1] * ir;
+    v = c[2] * ir;
+    w = c[3] * ir;
+    const FT p = gm1 * (c[4] - FT(0.5) * (c[1] * u + c[2] * v + c[3] * w));
+    T = gamma * p * ir;
+}
+
+// FP64 u, v, T of a cell next to the interface; contraction off and the same
+// code in the tiles on both sides, so both obtain the same bits.
+__device__ __forceinline__ void interface_cell3(const double* c, double gamma, double gm1, double& u,
+                                                double& v, double& T)
+{
+#pragma clang fp contract(off)
+    const double ir = rcp_nr(c[0]);
+    u = c[1] * ir;
+    v = c[2] * ir;
+    const double w = c[3] * ir;
+    const double p = gm1 * (c[4] - 0.5 * (c[1] * u + c[2] * v + c[3] * w));
+    T = gamma * p * ir;
+}
+
+// Interface viscous flux in +z (Appendix B, eq. bulk-flux with b_v = b_u):
+// (0, sigma_xz, sigma_yz, 0, u_w sigma_xz + v_w sigma_yz - Pi_z).
+__device__ __forceinline__ void interface_flux3(const StageArgs& A, double u1, double v1, double T1,
+                                                double u2, double v2, double T2, double* f)
+{
+#pragma clang fp contract(off)
+    const double sx = A.bu * (u2 - u1);
+    const double sy = A.bu * (v2 - v1);
+    const double pi = -A.bT * (T2 - T1);
+    const double uw = u1 + sx * A.half_dz1_mu1;
+    const double vw = v1 + sy * A.half_dz1_mu1;
+    f[0] = sx;
+    f[1] = sy;
+    f[2] = uw * sx + vw * sy - pi;
+}
+
+// Numerical flux through the face between tile cell (x, y, z) and its +dir
+// neighbour, in the components (rho, rho u, rho v, rho w, rho E).  Kinds as
+// in 2D (F3_TOP / F3_BOTTOM: mirror faces in z, no viscous part).
+template <class FT, int dir, class S>
+__device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, const Lds3<FT>& L, int x,
+                                      int y, int z, int kind, FT F[NV3])
+{
+#pragma clang fp contract(off)
+    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT h = FT(0.5), q4 = FT(0.25);
+    constexpr int sn = dir == 0 ? 1 : (dir == 1 ? S::HX : S::QPL);
+    constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;   // tangential directions
+    constexpr int plane = S::HZ * S::QPL;
+    // components in the face frame: rho, normal, tangential 1, tangential 2, energy
+    constexpr int comp[NV3] = {0, 1 + dir, 1 + t1, 1 + t2, 4};
+
+    FT qL[NV3], qR[NV3];
+    const int base = q3<S>(0, z, y, x);
+#pragma unroll
+    for (int k = 0; k < NV3; ++k) {
+        const FT* s = L.q + comp[k] * plane + base;
+        const FT qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
+        qL[k] = fma(q4, q1 - qm, q0);
+        qR[k] = fma(-q4, q2 - q0, q1);
+    }
+    if (kind == F3_TOP) {
+        qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3]; qR[4] = qL[4];
+    } else if (kind == F3_BOTTOM) {
+        qL[0] = qR[0]; qL[1] = -qR[1]; qL[2] = qR[2]; qL[3] = qR[3]; qL[4] = qR[4];
+    }
+    const FT yL = Fm<FT>::rsqrt(qL[0]), yR = Fm<FT>::rsqrt(qR[0]);
+    const FT rL = yL * yL, rR = yR * yR;
+    const FT sL = qL[0] * yL, sR = qR[0] * yR;
+    const FT unL = qL[1] * rL, a1L = qL[2] * rL, a2L = qL[3] * rL;
+    const FT unR = qR[1] * rR, a1R = qR[2] * rR, a2R = qR[3] * rR;
+    const FT pL = gm1 * fma(-h, fma(qL[1], unL, fma(qL[2], a1L, qL[3] * a2L)), qL[4]);
+    const FT pR = gm1 * fma(-h, fma(qR[1], unR, fma(qR[2], a1R, qR[3] * a2R)), qR[4]);
+    const FT aL = Fm<FT>::ws_sqrt(gamma * pL * rL);
+    const FT aR = Fm<FT>::ws_sqrt(gamma * pR * rR);
+    const FT iw = Fm<FT>::ws_rcp(sL + sR);
+    const FT unr = fma(sL, unL, sR * unR) * iw;
+    const FT a1r = fma(sL, a1L, sR * a1R) * iw;
+    const FT a2r = fma(sL, a2L, sR * a2R) * iw;
+    const FT HL = (qL[4] + pL) * rL, HR = (qR[4] + pR) * rR;
+    const FT Hr = fma(sL, HL, sR * HR) * iw;
+    const FT ar = Fm<FT>::ws_sqrt(gm1 * fma(-h, fma(unr, unr, fma(a1r, a1r, a2r * a2r)), Hr));
+    const FT lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
+    FT Fn[NV3];
+    if (kind != F3_INTERIOR) {
+        // Against its mirror image: (0, rho u_n^2 + p +- lambda rho u_n, 0, 0, 0).
+        Fn[0] = FT(0);
+        Fn[1] = (kind == F3_TOP) ? fma(lam, qL[1], fma(qL[1], unL, pL)) : fma(-lam, qR[1], fma(qR[1], unR, pR));
+        Fn[2] = FT(0);
+        Fn[3] = FT(0);
+        Fn[4] = FT(0);
+    } else {
+        const FT hl = h * lam;
+        Fn[0] = fma(-hl, qR[0] - qL[0], h * (qL[1] + qR[1]));
+        Fn[1] = fma(-hl, qR[1] - qL[1], h * (fma(qL[1], unL, qR[1] * unR) + (pL + pR)));
+        Fn[2] = fma(-hl, qR[2] - qL[2], h * fma(qL[2], unL, qR[2] * unR));
+        Fn[3] = fma(-hl, qR[3] - qL[3], h * fma(qL[3], unL, qR[3] * unR));
+        Fn[4] = fma(-hl, qR[4] - qL[4], h * fma(qL[4] + pL, unL, (qR[4] + pR) * unR));
+
+        // Viscous part (Appendix B): common velocity, normal derivatives by
+        // finite difference, tangential ones by averaging the cell gradients.
+        constexpr int pn = dir == 0 ? 1 : (dir == 1 ? S::PX : S::PPL);
+        constexpr int ps[3] = {1, S::PX, S::PPL};
+        constexpr int pp = S::PZ * S::PPL;
+        const int pb = p3<S>(0, z, y, x);
+        const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+        // g[c][d]: d u_c / d x_d at the face, c, d in (x, y, z)
+        FT g[3][3], uh[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const FT* U = L.p + c * pp + pb;
+            uh[c] = h * (U[0] + U[pn]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (d == dir) {
+                    g[c][d] = (U[pn] - U[0]) * inv_h[d];
+                } else {
+                    const int st = ps[d];
+                    g[c][d] = ((U[st] - U[-st]) + (U[pn + st] - U[pn - st])) * (q4 * inv_h[d]);
+                }
+            }
+        }
+        const FT* Tt = L.p + 3 * pp + pb;
+        const FT Tn = (Tt[pn] - Tt[0]) * inv_h[dir];
+        const FT mu = FT(D.mu);
+        FT sg[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            sg[c] = (c == dir) ? mu * fma(FT(4.0 / 3.0), g[dir][dir], FT(-2.0 / 3.0) * (g[t1][t1] + g[t2][t2]))
+                               : mu * (g[dir][c] + g[c][dir]);
+        const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], FT(D.kappa) * Tn)));
+        Fn[1] = Fn[1] - sg[dir];
+        Fn[2] = Fn[2] - sg[t1];
+        Fn[3] = Fn[3] - sg[t2];
+        Fn[4] = Fn[4] - en;
+    }
+    // back to (rho, rho u, rho v, rho w, rho E)
+    F[0] = Fn[0];
+    F[1 + dir] = Fn[1];
+    F[1 + t1] = Fn[2];
+    F[1 + t2] = Fn[3];
+    F[4] = Fn[4];
+}
+
+template <int DOM, class FT>
+__device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* smem)
+{
+    using S = typename TileOf<FT>::S;
+    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
+    constexpr int HX = S::HX, HY = S::HY, HZ = S::HZ, PX = S::PX, PY = S::PY, PZ = S::PZ;
+    const DomainArgs& D = A.d[DOM];
+    const DomainArgs& O = A.d[1 - DOM];
+    const int tid = threadIdx.x;
+    const int nx = A.nx, ny = A.ny, nz = D.nz;
+    const int tx = tile % D.tiles_x;
+    const int ty = (tile / D.tiles_x) % D.tiles_y;
+    const int tz = tile / (D.tiles_x * D.tiles_y);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = (D.row_lo / TZ + tz) * TZ;
+    const int vs = max(z0, D.row_lo) - z0;
+    const int ve = min(z0 + TZ, D.row_hi) - z0;
+    const int ncx = min(TX, nx - x0), ncy = min(TY, ny - y0);
+    const size_t rowsz = (size_t)ny * nx;
+
+    Lds3<FT> L;
+    L.q = (FT*)smem;
+    L.p = L.q + S::LDS_Q;
+    L.gf = (double*)(smem + (S::LDS_Q + S::LDS_P) * sizeof(FT));
+    FT* ex_x = L.q;                       // [5][TZ][TY][TX+1]
+    FT* ex_y = ex_x + NV3 * S::EXX;       // [5][TZ][TY+1][TX]
+    FT* ex_z = ex_y + NV3 * S::EXY;       // [5][TZ+1][TY][TX]
+
+    const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + ve == nz) : (D.gamma_bot && z0 + vs == 0);
+
+    const int cx = tid % TX;
+    const int cy = (tid / TX) % TY;
+    const int r0 = 2 * (tid / (TX * TY));
+    const bool inxy = cx < ncx && cy < ncy;
+    const bool ok0 = inxy && r0 >= vs && r0 < ve;
+    const bool ok1 = inxy && r0 + 1 >= vs && r0 + 1 < ve;
+
+    // ---- stage the state (x, y periodic; mirror planes beyond the domain;
+    // retained slow planes at substeps 2..m)
+    constexpr int NCELL = HZ * HY * HX;
+    for (int idx0 = tid; idx0 < NCELL; idx0 += 2 * NT) {
+        double val[2][NV3];
+        bool neg[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = idx0 + u * NT;
+            neg[u] = false;
+            if (idx < NCELL) {
+                const int zz = idx / (HY * HX), rem = idx - zz * (HY * HX);
+                const int yy = rem / HX, xx = rem - yy * HX;
+                const int col = wrapx(x0 + xx - 2, nx), rowy = wrapx(y0 + yy - 2, ny);
+                int pl = z0 + zz - 2;
+                if (pl < 0) { pl = 0; neg[u] = true; }
+                else if (pl >= nz) { pl = nz - 1; neg[u] = true; }
+                const double* src;
+                size_t vstride;
+                if (D.use_ret && (pl < D.b_lo || pl >= D.b_hi)) {
+                    int rr = pl - D.ret_lo;
+                    rr = rr < 0 ? 0 : (rr > 1 ? 1 : rr);
+                    src = D.ret_in + (size_t)rr * rowsz + (size_t)rowy * nx + col;
+                    vstride = 2 * rowsz;
+                } else {
+                    src = D.qin + (size_t)pl * rowsz + (size_t)rowy * nx + col;
+                    vstride = (size_t)nz * rowsz;
+                }
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) val[u][v] = src[v * vstride];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = idx0 + u * NT;
+            if (idx < NCELL) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v)
+                    L.q[v * NCELL + idx] = FT((v == 3 && neg[u]) ? -val[u][v] : val[u][v]);
+            }
+        }
+    }
+    // Interface flux per column, FP64 from the FP64 cells next to the lid.
+    if (has_gamma) {
+        for (int c = tid; c < TX * TY; c += NT) {
+            const int xx = c % TX, yy = c / TX;
+            const int col = wrapx(x0 + xx, nx), rowy = wrapx(y0 + yy, ny);
+            const int own = (DOM == 0) ? nz - 1 : 0;
+            const int oth = (DOM == 0) ? 0 : O.nz - 1;
+            const size_t po = (size_t)nz * rowsz, pq = (size_t)O.nz * rowsz;
+            const double* a = D.qin + (size_t)own * rowsz + (size_t)rowy * nx + col;
+            const double* b = O.qin + (size_t)oth * rowsz + (size_t)rowy * nx + col;
+            double ca[NV3], cb[NV3];
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) { ca[v] = a[v * po]; cb[v] = b[v * pq]; }
+            double ua, va, Ta, ub, vb, Tb, f[3];
+            interface_cell3(ca, A.gamma, A.gm1, ua, va, Ta);
+            interface_cell3(cb, A.gamma, A.gm1, ub, vb, Tb);
+            if (DOM == 0) interface_flux3(A, ua, va, Ta, ub, vb, Tb, f);
+            else interface_flux3(A, ub, vb, Tb, ua, va, Ta, f);
+            L.gf[c] = f[0];
+            L.gf[TX * TY + c] = f[1];
+            L.gf[2 * TX * TY + c] = f[2];
+        }
+    }
+    __syncthreads();
+
+    // ---- primitives on the tile plus a 1-cell ring
+    constexpr int NPC = PZ * PY * PX;
+    for (int idx = tid; idx < NPC; idx += NT) {
+        const int zz = idx / (PY * PX), rem = idx - zz * (PY * PX);
+        const int yy = rem / PX, xx = rem - yy * PX;
+        const int b = q3<S>(0, zz - 1, yy - 1, xx - 1);
+        FT c[NV3];
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) c[v] = L.q[v * NCELL + b];
+        FT u, v, w, T;
+        prim3<FT>(c, FT(A.gamma), FT(A.gm1), u, v, w, T);
+        L.p[idx] = u;
+        L.p[NPC + idx] = v;
+        L.p[2 * NPC + idx] = w;
+        L.p[3 * NPC + idx] = T;
+    }
+    __syncthreads();
+
+    // ---- faces: x+, y+, z+ of the thread's two cells, then the edge faces
+    // (x left of column 0, y in front of row 0, z below the first computed
+    // plane), all kept in registers or written after the barrier.
+    FT F[6][NV3];
+    const int kz0 = (z0 + r0 == nz - 1) ? F3_TOP : F3_INTERIOR;
+    const int kz1 = (z0 + r0 + 1 == nz - 1) ? F3_TOP : F3_INTERIOR;
+    if (ok0) {
+        face3<FT, 0, S>(A, D, L, cx, cy, r0, F3_INTERIOR, F[0]);
+        face3<FT, 1, S>(A, D, L, cx, cy, r0, F3_INTERIOR, F[1]);
+        face3<FT, 2, S>(A, D, L, cx, cy, r0, kz0, F[2]);
+    }
+    if (ok1) {
+        face3<FT, 0, S>(A, D, L, cx, cy, r0 + 1, F3_INTERIOR, F[3]);
+        face3<FT, 1, S>(A, D, L, cx, cy, r0 + 1, F3_INTERIOR, F[4]);
+        face3<FT, 2, S>(A, D, L, cx, cy, r0 + 1, kz1, F[5]);
+    }
+    // Edge faces: ne_x = TY*TZ (x = -1), ne_y = TX*TZ (y = -1), ne_z = TX*TY (below vs).
+    constexpr int NEX = TY * TZ, NEY = TX * TZ, NEZ = TX * TY, NE = NEX + NEY + NEZ;
+    constexpr int EPT = (NE + NT - 1) / NT;
+    FT E[EPT][NV3];
+    int ekind[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * NT;
+        ekind[u] = -1;
+        if (e < NEX) {
+            const int yy = e % TY, zz = e / TY;
+            if (yy < ncy && zz >= vs && zz < ve) {
+                face3<FT, 0, S>(A, D, L, -1, yy, zz, F3_INTERIOR, E[u]);
+                ekind[u] = 0;
+            }
+        } else if (e < NEX + NEY) {
+            const int f = e - NEX, xx = f % TX, zz = f / TX;
+            if (xx < ncx && zz >= vs && zz < ve) {
+                face3<FT, 1, S>(A, D, L, xx, -1, zz, F3_INTERIOR, E[u]);
+                ekind[u] = 1;
+            }
+        } else if (e < NE) {
+            const int f = e - NEX - NEY, xx = f % TX, yy = f / TX;
+            if (xx < ncx && yy < ncy) {
+                const int kind = (z0 + vs == 0) ? F3_BOTTOM : F3_INTERIOR;
+                face3<FT, 2, S>(A, D, L, xx, yy, vs - 1, kind, E[u]);
+                ekind[u] = 2;
+            }
+        }
+    }
+
+    // FP64 pointwise reads for the combination (the stage value itself when
+    // the fluxes are FP32; the substep base U).
+    const int col = x0 + cx, rowy = y0 + cy;
+    const size_t plane = (size_t)nz * rowsz;
+    const size_t nbx = (size_t)(D.b_hi - D.b_lo) * rowsz;
+    double qc[2][NV3], Ub[2][NV3];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int row = z0 + r0 + hh;
+        const bool ok = hh ? ok1 : ok0;
+        const bool inb = (row >= D.b_lo && row < D.b_hi);
+        const Combine& cb = inb ? D.buf : D.main;
+        const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) {
+            Ub[hh][v] = 0.0;
+            qc[hh][v] = sizeof(FT) == 8 ? (double)L.q[q3<S>(v, r0 + hh, cy, cx)] : 0.0;
+        }
+        if (ok && sizeof(FT) != 8) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) qc[hh][v] = D.qin[v * plane + id];
+        }
+        if (ok && cb.mode != MODE_RHS && cb.alpha != 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) Ub[hh][v] = D.base[v * plane + id];
+        }
+    }
+    __syncthreads();   // all LDS reads of the staged state are done
+
+    auto put = [&](int d, int xx, int yy, int zz, const FT* f) {
+        FT* e;
+        int st;
+        if (d == 0) { e = ex_x + (zz * TY + yy) * (TX + 1) + xx + 1; st = S::EXX; }
+        else if (d == 1) { e = ex_y + (zz * (TY + 1) + yy + 1) * TX + xx; st = S::EXY; }
+        else { e = ex_z + ((zz + 1) * TY + yy) * TX + xx; st = S::EXZ; }
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) e[v * st] = f[v];
+    };
+    if (ok0) { put(0, cx, cy, r0, F[0]); put(1, cx, cy, r0, F[1]); put(2, cx, cy, r0, F[2]); }
+    if (ok1) { put(0, cx, cy, r0 + 1, F[3]); put(1, cx, cy, r0 + 1, F[4]); put(2, cx, cy, r0 + 1, F[5]); }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * NT;
+        if (ekind[u] == 0) put(0, -1, e % TY, e / TY, E[u]);
+        else if (ekind[u] == 1) { const int f = e - NEX; put(1, f % TX, -1, f / TX, E[u]); }
+        else if (ekind[u] == 2) { const int f = e - NEX - NEY; put(2, f % TX, f / TX, vs - 1, E[u]); }
+    }
+    __syncthreads();
+
+    // ---- divergence (FP64), interface flux, source, stage combination
+    const double inv_dx = A.inv_dx, inv_dy = A.inv_dy, inv_dz = D.inv_dz;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const bool ok = hh ? ok1 : ok0;
+        if (!ok) continue;
+        const int zz = r0 + hh;
+        const int row = z0 + zz;
+        double R[NV3];
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) {
+            const FT* fx = ex_x + v * S::EXX + (zz * TY + cy) * (TX + 1) + cx;
+            const FT* fy = ex_y + v * S::EXY + (zz * (TY + 1) + cy) * TX + cx;
+            const FT* fz = ex_z + v * S::EXZ + (zz * TY + cy) * TX + cx;
+            R[v] = -((double)fx[1] - (double)fx[0]) * inv_dx - ((double)fy[TX] - (double)fy[0]) * inv_dy -
+                   ((double)fz[TY * TX] - (double)fz[0]) * inv_dz;
+        }
+        const int gc = cy * TX + cx;
+        if (DOM == 0 && D.gamma_top && row == nz - 1) {
+            R[1] += L.gf[gc] * inv_dz;
+            R[2] += L.gf[TX * TY + gc] * inv_dz;
+            R[4] += L.gf[2 * TX * TY + gc] * inv_dz;
+        }
+        if (DOM == 1 && D.gamma_bot && row == 0) {
+            R[1] -= L.gf[gc] * inv_dz;
+            R[2] -= L.gf[TX * TY + gc] * inv_dz;
+            R[4] -= L.gf[2 * TX * TY + gc] * inv_dz;
+        }
+        R[3] += qc[hh][0] * A.gravity;
+        R[4] += qc[hh][3] * A.gravity;
+
+        const bool inb = (row >= D.b_lo && row < D.b_hi);
+        const Combine& cb = inb ? D.buf : D.main;
+        const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
+        if (cb.mode == MODE_RHS) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = R[v];
+        } else if (cb.alpha == 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = qc[hh][v] + cb.bh * R[v];
+        } else {
+            double inc[NV3];
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) inc[v] = cb.beta * (qc[hh][v] - Ub[hh][v]) + cb.bh * R[v];
+            if (cb.mode == MODE_STAGE) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = Ub[hh][v] + inc[v];
+            } else {
+                const size_t ia = (size_t)(row - D.b_lo) * rowsz + (size_t)rowy * nx + col;
+                if (cb.mode == MODE_ACC_FIRST) {
+#pragma unroll
+                    for (int v = 0; v < NV3; ++v) D.acc[v * nbx + ia] = inc[v];
+                } else if (cb.mode == MODE_ACC_ADD) {
+#pragma unroll
+                    for (int v = 0; v < NV3; ++v) D.acc[v * nbx + ia] += inc[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV3; ++v)
+                        D.out[v * plane + id] = Ub[hh][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m;
+                }
+            }
+        }
+        if (D.ret_out && row >= D.ret_lo && row < D.ret_lo + 2) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v)
+                D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * rowsz + (size_t)rowy * nx + col] = qc[hh][v];
+        }
+    }
+}
+
+template <class FT>
+__global__ __launch_bounds__(TileOf<FT>::S::NT) void stage_kernel3(const StageArgs A)
+{
+    using S = typename TileOf<FT>::S;
+    __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
+    const int b = blockIdx.x;
+    const int n0 = A.d[A.first].ntiles;
+    const int dom = (b < n0) ? A.first : 1 - A.first;
+    const int t = (b < n0) ? b : b - n0;
+    if (dom == 0) stage_tile3<0, FT>(A, t, smem);
+    else stage_tile3<1, FT>(A, t, smem);
+}
+
+}  // namespace
+
+hipError_t launch_stage3(const StageArgs& a, hipStream_t s)
+{
+    if (a.nblocks <= 0) return hipSuccess;
+    if (a.flux32) hipLaunchKernelGGL(stage_kernel3<float>, dim3(a.nblocks), dim3(T32::NT), 0, s, a);
+    else hipLaunchKernelGGL(stage_kernel3<double>, dim3(a.nblocks), dim3(T64::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+KernelRef stage3_kernel_ref(bool flux32)
+{
+    if (flux32) return KernelRef{(const void*)stage_kernel3<float>, T32::NT};
+    return KernelRef{(const void*)stage_kernel3<double>, T64::NT};
+}
+
+TileDims3 tile3_dims(bool flux32)
+{
+    if (flux32) return {T32::TX, T32::TY, T32::TZ, T32::NT};
+    return {T64::TX, T64::TY, T64::TZ, T64::NT};
+}
+
+}  // namespace mprk

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, EBUFFER, EWORKSPACE, EHIP, ENONFINITE, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 EXEC_LAUNCH, EXEC_PERSISTENT, EXEC_GRAPH = 0, 1, 2
 TILE_32X16, TILE_16X32, TILE_64X8, TILE_32X8, TILE_SHAPES = 0, 1, 2, 3, 4
@@ -51,8 +51,8 @@ class mprk_config(ctypes.Structure):
 
 class mprk_stats(ctypes.Structure):
     _fields_ = [
-        ("totals_lower", ctypes.c_double * 4),
-        ("totals_upper", ctypes.c_double * 4),
+        ("totals_lower", ctypes.c_double * 5),
+        ("totals_upper", ctypes.c_double * 5),
         ("lambda_lower", ctypes.c_double),
         ("lambda_upper", ctypes.c_double),
         ("courant_lower", ctypes.c_double),
@@ -318,6 +318,15 @@ def config(nx, nz_lower, nz_upper, dx, dz_lower, dz_upper, *, fast_is_lower=True
                        mu_upper, gravity, flux_bits, strict_buffer)
 
 
+def config3_of_workload(w, **over) -> mprk_config:
+    """Configuration of a 3D workload (inputs.Workload3)."""
+    kw = dict(fast_is_lower=w.fast_is_lower, n_buffer=w.n_buffer, base_rk=w.base, m=w.m,
+              gamma=w.gamma, prandtl=w.prandtl, mu_lower=w.mu_lower, mu_upper=w.mu_upper,
+              gravity=w.gravity, dim=3, ny=w.ny, dy=w.dy)
+    kw.update(over)
+    return config(w.nx, w.nz_lower, w.nz_upper, w.dx, w.dz_lower, w.dz_upper, **kw)
+
+
 def config_of_workload(w, **over) -> mprk_config:
     kw = dict(fast_is_lower=w.fast_is_lower, n_buffer=w.n_buffer, base_rk=w.base, m=w.m,
               gamma=w.gamma, prandtl=w.prandtl, mu_lower=w.mu_lower, mu_upper=w.mu_upper,
@@ -341,8 +350,11 @@ class Solver:
         for t in (q_lower, q_upper):
             if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError("state must be contiguous float64 device tensors")
-        if tuple(q_lower.shape) != (4, cfg.nz_lower, cfg.nx) or \
-                tuple(q_upper.shape) != (4, cfg.nz_upper, cfg.nx):
+        if cfg.dim == 3:
+            want = (5, cfg.nz_lower, cfg.ny, cfg.nx), (5, cfg.nz_upper, cfg.ny, cfg.nx)
+        else:
+            want = (4, cfg.nz_lower, cfg.nx), (4, cfg.nz_upper, cfg.nx)
+        if tuple(q_lower.shape) != want[0] or tuple(q_upper.shape) != want[1]:
             raise ValueError("state shapes do not match the configuration")
         rc, msg = mprk_validate(cfg)
         _check(rc, "mprk_validate: " + msg)

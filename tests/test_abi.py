@@ -37,7 +37,10 @@ def _cfg(**kw):
 @pytest.mark.parametrize("over,code", [
     ({}, mprk.OK),
     ({"abi_version": 99}, mprk.EINVAL),
-    ({"dim": 3}, mprk.EUNSUPPORTED),
+    ({"dim": 3}, mprk.EINVAL),
+    ({"dim": 3, "ny": 8, "dy": 0.1}, mprk.OK),
+    ({"dim": 3, "ny": 8, "dy": 0.0}, mprk.EINVAL),
+    ({"dim": 3, "ny": 3, "dy": 0.1}, mprk.EINVAL),
     ({"dim": 1}, mprk.EINVAL),
     ({"ny": 2}, mprk.EINVAL),
     ({"nx": 3}, mprk.EINVAL),
@@ -83,7 +86,7 @@ def test_workspace_bytes():
         tot = (s - 1) * (a(n_lo) + a(n_up))
         if cfg.m > 1:
             tot += s * a(4 * 2 * cfg.nx * 8) + a(4 * cfg.n_buffer * cfg.nx * 8)
-        tot += a(2 * 256 * 12 * 8) + a(2 * 12 * 8)
+        tot += a(2 * 256 * 14 * 8) + a(2 * 14 * 8)
         return tot
 
     def tables(cfg):
@@ -220,3 +223,18 @@ def test_serving_footprint_and_budget_check():
     srv = serving.Server("cpu", fp - 1)
     with pytest.raises(ValueError):
         srv.run([serving.Request(0, cfg, ql, qu, 5)])
+
+
+def test_workspace_bytes_3d():
+    w = inputs.small3d()
+    cfg = mprk.config3_of_workload(w)
+    a = lambda n: (n + 255) // 256 * 256
+    plane = w.nx * w.ny * 8
+    core = (w.base - 1) * (a(5 * w.nz_lower * plane) + a(5 * w.nz_upper * plane))
+    core += w.base * a(5 * 2 * plane) + a(5 * w.n_buffer * plane)
+    core += a(2 * 256 * 14 * 8) + a(2 * 14 * 8)
+    got = mprk.mprk_workspace_bytes(cfg)
+    assert core < got <= core + w.m * w.base * 2048 + 64 * 1024
+    # batches hold 2D problems only
+    m = mprk.mprk_member(cfg, 1 << 20, 1 << 28, 0.01)
+    assert mprk.mprk_batch_validate([m])[0] == mprk.EUNSUPPORTED

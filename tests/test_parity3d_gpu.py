@@ -1,0 +1,194 @@
+"""3D parity: the HIP 3D stage kernel through the C ABI against the FP64 3D
+oracle (Appendix B in three dimensions).
+
+Tolerances as in 2D: a single RHS within 1e-13 of the flux scale (FP64
+fluxes) or 200 FP32 unit roundoffs (FP32 fluxes); states after N steps within
+1e-12 (FP64) or 1e-5 (FP32) of the component scale; conservation and the free
+stream exact to FP64 rounding in both precisions.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_11890_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2202_11890_amd import mprk  # noqa: E402
+from tests.test_oracle3d_pins import prob3  # noqa: E402
+
+DEV = torch.device("cuda:0")
+U32 = float(np.finfo(np.float32).eps) / 2
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def scale3(q, gamma=1.4):
+    rho = q[0]
+    vel = q[1:4] / rho
+    p = (gamma - 1) * (q[4] - 0.5 * rho * (vel ** 2).sum(axis=0))
+    a = np.sqrt(gamma * p / rho).max()
+    mom = max(np.abs(q[1:4]).max(), 1e-3 * rho.max() * a)
+    return np.array([np.abs(q[0]).max(), mom, mom, mom, np.abs(q[4]).max()])
+
+
+def state_err3(got, ref):
+    return np.abs(got - ref).max(axis=(1, 2, 3)) / scale3(ref)
+
+
+def rhs_scale3(q, hmin, gamma=1.4):
+    rho = q[0]
+    vel = q[1:4] / rho
+    p = (gamma - 1) * (q[4] - 0.5 * rho * (vel ** 2).sum(axis=0))
+    a = np.sqrt(gamma * p / rho)
+    s = np.abs(vel).sum(axis=0) + a
+    out = [(np.abs(q[v]) * s).max() for v in range(5)]
+    for v in (1, 2, 3):
+        out[v] += (p * s).max()
+    out[4] += (p * s).max()
+    return np.array(out) / hmin
+
+
+CASES = [
+    ("small", inputs.small3d()),
+    ("ragged", inputs.small3d().with_(nx=21, ny=13, nz_lower=9, nz_upper=7, m=3, n_buffer=5)),
+    ("fast-upper", inputs.small3d().with_(nx=18, ny=10, nz_lower=11, nz_upper=8, fast_is_lower=False,
+                                          lz_lower=5.0, lz_upper=1.0, n_buffer=5)),
+    ("viscous", inputs.small3d().with_(mu_lower=5e-3, mu_upper=2e-3, t_lower=2.0, gravity=-0.05)),
+]
+
+
+def run_gpu3(w, ql, qu, dt, n, flux_bits=64, exec_mode=None):
+    tl, tu = dev(ql), dev(qu)
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=flux_bits), tl, tu, exec_mode=exec_mode)
+    st = sol.run(dt, n)
+    torch.cuda.synchronize()
+    out = tl.cpu().numpy(), tu.cpu().numpy()
+    sol.close()
+    return out, st
+
+
+@pytest.mark.parametrize("name,w", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("flux_bits", [64, 32])
+@pytest.mark.parametrize("kind", ["smooth", "random"])
+def test_rhs3_matches_oracle(name, w, flux_bits, kind):
+    say("rhs3", name, flux_bits, kind)
+    if kind == "smooth":
+        ql, qu = inputs.initial_state3(w)
+    else:
+        ql, qu = inputs.random_state3(w, 3, amp=0.1)
+    rl, ru = oracle.rhs3(prob3(w), ql, qu)
+    tl, tu = dev(ql), dev(qu)
+    gl, gu = torch.full_like(tl, np.nan), torch.full_like(tu, np.nan)
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=flux_bits), tl, tu)
+    sol.rhs(tl, tu, gl, gu)
+    torch.cuda.synchronize()
+    tol = 1e-13 if flux_bits == 64 else 200 * U32
+    for g, r, q, dz in ((gl, rl, ql, w.dz_lower), (gu, ru, qu, w.dz_upper)):
+        err = np.abs(g.cpu().numpy() - r).max(axis=(1, 2, 3)) / rhs_scale3(q, min(w.dx, w.dy, dz))
+        say("  err / flux scale", err)
+        assert np.all(np.isfinite(err)) and np.all(err <= tol), err
+    sol.close()
+
+
+RUNS = [
+    ("small-m2", inputs.small3d(), 10),
+    ("rk2-m4", inputs.small3d().with_(base=2, m=4, n_buffer=3), 8),
+    ("sr", inputs.small3d().with_(m=1), 6),
+    ("ragged-m3", CASES[1][1], 6),
+    ("fast-upper", CASES[2][1], 6),
+]
+
+
+@pytest.mark.parametrize("name,w,n", RUNS, ids=[c[0] for c in RUNS])
+def test_run3_matches_oracle(name, w, n):
+    ql, qu = inputs.initial_state3(w)
+    pb = prob3(w)
+    dt = oracle.dt_rule3(pb, ql, qu, w.m)
+    (gl, gu), st = run_gpu3(w, ql, qu, dt, n)
+    ol, ou = ql.copy(), qu.copy()
+    oracle.mprk_run3(pb, w.base, w.m, dt, n, ol, ou)
+    el, eu = state_err3(gl, ol), state_err3(gu, ou)
+    say("run3", name, "err", el, eu)
+    assert st["status"] == 0
+    assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
+    (fl, fu), _ = run_gpu3(w, ql, qu, dt, n, flux_bits=32)
+    el, eu = state_err3(fl, ol), state_err3(fu, ou)
+    say("run3 fp32", name, "err", el, eu)
+    assert np.all(el <= 1e-5) and np.all(eu <= 1e-5)
+
+
+@pytest.mark.parametrize("flux_bits", [64, 32])
+def test_conservation3_on_gpu(flux_bits):
+    w = inputs.small3d().with_(nx=16, ny=12, nz_lower=8, nz_upper=8, n_buffer=5)
+    ql, qu = inputs.random_state3(w, 3, amp=0.05)
+    pb = prob3(w)
+    dt = oracle.dt_rule3(pb, ql, qu, w.m)
+    tl, tu = dev(ql), dev(qu)
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=flux_bits), tl, tu)
+    s0 = sol.diagnostics()
+    assert np.allclose(np.array([s0["totals_lower"], s0["totals_upper"]]), oracle.totals3(pb, ql, qu),
+                       rtol=1e-14, atol=1e-15)
+    s1 = sol.run(dt, 12)
+    sol.close()
+    t0 = np.array([s0["totals_lower"], s0["totals_upper"]])
+    t1 = np.array([s1["totals_lower"], s1["totals_upper"]])
+    assert abs(t1[0, 0] - t0[0, 0]) <= 1e-13 * t0[0, 0]
+    assert abs(t1[1, 0] - t0[1, 0]) <= 1e-13 * t0[1, 0]
+    for v in (1, 2):
+        assert abs(t1[:, v].sum() - t0[:, v].sum()) <= 1e-13 * t0[:, 0].sum()
+    assert abs(t1[:, 4].sum() - t0[:, 4].sum()) <= 1e-13 * t0[:, 4].sum()
+
+
+@pytest.mark.parametrize("flux_bits", [64, 32])
+def test_free_stream3_bitwise(flux_bits):
+    w = inputs.small3d().with_(nx=12, ny=10, nz_lower=6, nz_upper=7)
+    ql, qu = inputs.uniform_state3(w, 1.0, 0.3, -0.2, 0.0, 1 / 1.4)
+    (gl, gu), _ = run_gpu3(w, ql, qu, 0.01, 3, flux_bits=flux_bits)
+    assert np.array_equal(gl, ql) and np.array_equal(gu, qu)
+
+
+def test_graph_mode3_bitwise():
+    w = CASES[1][1]
+    ql, qu = inputs.initial_state3(w)
+    dt = oracle.dt_rule3(prob3(w), ql, qu, w.m)
+    out = []
+    for mode in (mprk.EXEC_LAUNCH, mprk.EXEC_GRAPH):
+        tl, tu = dev(ql), dev(qu)
+        sol = mprk.Solver(mprk.config3_of_workload(w), tl, tu, exec_mode=mode)
+        sol.run(dt, 2)
+        sol.run(dt, 3)
+        torch.cuda.synchronize()
+        out.append((tl.cpu().numpy(), tu.cpu().numpy()))
+        sol.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_rhs3_full_size():
+    """The 256 x 256 x 128 (x2) workload: one FP64 RHS against the oracle."""
+    w = inputs.large3d()
+    say("rhs3 full size", w.nx, w.ny, w.nz_lower)
+    ql, qu = inputs.initial_state3(w)
+    rl, ru = oracle.rhs3(prob3(w), ql, qu)
+    tl, tu = dev(ql), dev(qu)
+    gl, gu = torch.empty_like(tl), torch.empty_like(tu)
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=64), tl, tu)
+    sol.rhs(tl, tu, gl, gu)
+    torch.cuda.synchronize()
+    for g, r, q, dz in ((gl, rl, ql, w.dz_lower), (gu, ru, qu, w.dz_upper)):
+        err = np.abs(g.cpu().numpy() - r).max(axis=(1, 2, 3)) / rhs_scale3(q, min(w.dx, w.dy, dz))
+        say("  err / flux scale", err)
+        assert np.all(err <= 1e-13), err
+    sol.close()
