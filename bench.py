@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D run")
+    ap.add_argument("--steps-3d", type=int, default=None, help="default: the workload's 200")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--serving-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the measured saturated capacity")
@@ -343,6 +345,8 @@ def main():
         out["ensemble"] = ensemble_leg(args, torch, dev)
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, dev)
+    if not args.no_3d:
+        out["3d"] = leg_3d(args, torch, dev)
 
     print(json.dumps(out), flush=True)
 
@@ -465,6 +469,53 @@ def ensemble_leg(args, torch, dev):
         "single_rate": {"seconds": t_sr, "value": cs_sr * K / t_sr,
                         "time_to_solution_speedup": t_sr / t_graph,
                         "max_rel_diff_mprk_vs_single_rate": diff},
+    }
+
+
+def leg_3d(args, torch, dev):
+    """The 3D workload (two stacked 256x256x128 domains, dz_fast = dz_slow/4,
+    MPRK3 m = 4, FP32 flux / FP64 state): rate, per-launch kernel time from
+    HIP events around every stage launch, algorithmic HBM bandwidth."""
+    from paper_2202_11890_amd import costmodel, inputs, mprk
+
+    w = inputs.large3d()
+    K = args.steps_3d if args.steps_3d is not None else w.steps
+    ql, qu = inputs.initial_state3(w)
+    tl0, tu0 = torch.from_numpy(ql).to(dev), torch.from_numpy(qu).to(dev)
+    tl, tu = tl0.clone(), tu0.clone()
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=32), tl, tu)
+    dt = sol.stable_dt(w.cfl, w.dnum)
+    sol.run(dt, 2)
+    tl.copy_(tl0)
+    tu.copy_(tu0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sol.run(dt, K, check_every=args.check_every)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sol.profile(True)
+    for _ in range(5):
+        sol.step(dt)
+    k_ms, k_n = sol.profile_take()
+    sol.profile(False)
+    sol.close()
+    plane = w.nx * w.ny
+    nF, nB, nS = w.nz_lower * plane, w.n_buffer * plane, (w.nz_upper - w.n_buffer) * plane
+    cs = costmodel.mprk_cell_stages(nF, nB, nS, w.m, w.base)
+    # 5 FP64 components: read Q_j, read U except at stage 1, write Q_j+1
+    bytes_step = 40.0 * (3.0 - 1.0 / w.base) * cs
+    per_launch = bytes_step / (w.m * w.base)
+    avg = k_ms * 1e-3 / k_n
+    gbs = per_launch / avg / 1e9
+    print("# 3d: %d steps, %.3f ms/step, %.3e cell-stage/s, stage kernel %.1f us, %.0f GB/s" % (
+        K, 1e3 * t / K, cs * K / t, avg * 1e6, gbs), file=sys.stderr, flush=True)
+    return {
+        "workload": w.name + ", FP32 flux / FP64 state, dz_fast = dz_slow/4",
+        "value": cs * K / t, "unit": "cell-stage updates/s", "steps": K, "ms_per_step": 1e3 * t / K,
+        "dt": dt, "status": st["status"], "cell_stages_per_step": cs,
+        "stage_kernel": {"avg_launch_us_bracketed": avg * 1e6,
+                         "algorithmic_bytes_per_launch": int(per_launch),
+                         "achieved_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS},
     }
 
 
