@@ -3,7 +3,7 @@
 // domains stacked in z and coupled through the rigid lid).
 //
 // Same structure as the 2D kernel: a workgroup owns a TX x TY x TZ tile of one
-// domain; each thread owns a vertical pair of cells.  The conserved state
+// domain; each thread owns one cell (or a vertical run of cells).  The conserved state
 // (5 components, 2-cell halo) and the primitives u, v, w, T (1-cell halo) are
 // staged in LDS in the flux type; every face of the tile is evaluated once
 // (three per cell plus the left, front and bottom edge faces), exchanged
@@ -17,9 +17,10 @@ namespace mprk {
 
 namespace {
 
-template <int X, int Y, int Z>
+template <int X, int Y, int Z, int C>
 struct Shape3 {
-    static constexpr int TX = X, TY = Y, TZ = Z, NT = X * Y * Z / 2;
+    static constexpr int CZ = C;                        // cells per thread, stacked in z
+    static constexpr int TX = X, TY = Y, TZ = Z, NT = X * Y * Z / C;
     static constexpr int HX = X + 4, HY = Y + 4, HZ = Z + 4;
     static constexpr int PX = X + 2, PY = Y + 2, PZ = Z + 2;
     static constexpr int QPL = HY * HX;                 // staged state: one z-plane
@@ -28,14 +29,17 @@ struct Shape3 {
     static constexpr int LDS_P = 4 * PZ * PPL;          // u, v, w, T
     static constexpr int EXX = Z * Y * (X + 1), EXY = Z * (Y + 1) * X, EXZ = (Z + 1) * Y * X;
     static constexpr int LDS_EX = NV3 * (EXX + EXY + EXZ);
-    static_assert(Z % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
+    static_assert(Z % C == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
     static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
     template <class FT>
     static constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 3 * X * Y * 8; }
 };
 
-using T32 = Shape3<16, 8, 4>;     // FP32 fluxes: 256 threads, 55.7 KB
-using T64 = Shape3<8, 4, 4>;      // FP64 fluxes: 64 threads, 42.1 KB
+#ifndef MPRK3_CZ32
+#define MPRK3_CZ32 1
+#endif
+using T32 = Shape3<16, 8, 4, MPRK3_CZ32>;   // FP32 fluxes: 58.8 KB LDS
+using T64 = Shape3<8, 4, 4, 1>;             // FP64 fluxes: 43.0 KB LDS, 128 threads
 
 template <class FT> struct TileOf;
 template <> struct TileOf<float> { using S = T32; };
@@ -240,12 +244,14 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
 
     const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + ve == nz) : (D.gamma_bot && z0 + vs == 0);
 
+    constexpr int CZ = S::CZ;
     const int cx = tid % TX;
     const int cy = (tid / TX) % TY;
-    const int r0 = 2 * (tid / (TX * TY));
+    const int r0 = CZ * (tid / (TX * TY));
     const bool inxy = cx < ncx && cy < ncy;
-    const bool ok0 = inxy && r0 >= vs && r0 < ve;
-    const bool ok1 = inxy && r0 + 1 >= vs && r0 + 1 < ve;
+    bool okc[CZ];
+#pragma unroll
+    for (int hh = 0; hh < CZ; ++hh) okc[hh] = inxy && r0 + hh >= vs && r0 + hh < ve;
 
     // ---- stage the state (x, y periodic; mirror planes beyond the domain;
     // retained slow planes at substeps 2..m)
@@ -332,21 +338,17 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     }
     __syncthreads();
 
-    // ---- faces: x+, y+, z+ of the thread's two cells, then the edge faces
+    // ---- faces: x+, y+, z+ of the thread's cells, then the edge faces
     // (x left of column 0, y in front of row 0, z below the first computed
     // plane), all kept in registers or written after the barrier.
-    FT F[6][NV3];
-    const int kz0 = (z0 + r0 == nz - 1) ? F3_TOP : F3_INTERIOR;
-    const int kz1 = (z0 + r0 + 1 == nz - 1) ? F3_TOP : F3_INTERIOR;
-    if (ok0) {
-        face3<FT, 0, S>(A, D, L, cx, cy, r0, F3_INTERIOR, F[0]);
-        face3<FT, 1, S>(A, D, L, cx, cy, r0, F3_INTERIOR, F[1]);
-        face3<FT, 2, S>(A, D, L, cx, cy, r0, kz0, F[2]);
-    }
-    if (ok1) {
-        face3<FT, 0, S>(A, D, L, cx, cy, r0 + 1, F3_INTERIOR, F[3]);
-        face3<FT, 1, S>(A, D, L, cx, cy, r0 + 1, F3_INTERIOR, F[4]);
-        face3<FT, 2, S>(A, D, L, cx, cy, r0 + 1, kz1, F[5]);
+    FT F[3 * CZ][NV3];
+#pragma unroll
+    for (int hh = 0; hh < CZ; ++hh) {
+        if (!okc[hh]) continue;
+        const int kz = (z0 + r0 + hh == nz - 1) ? F3_TOP : F3_INTERIOR;
+        face3<FT, 0, S>(A, D, L, cx, cy, r0 + hh, F3_INTERIOR, F[3 * hh]);
+        face3<FT, 1, S>(A, D, L, cx, cy, r0 + hh, F3_INTERIOR, F[3 * hh + 1]);
+        face3<FT, 2, S>(A, D, L, cx, cy, r0 + hh, kz, F[3 * hh + 2]);
     }
     // Edge faces: ne_x = TY*TZ (x = -1), ne_y = TX*TZ (y = -1), ne_z = TX*TY (below vs).
     constexpr int NEX = TY * TZ, NEY = TX * TZ, NEZ = TX * TY, NE = NEX + NEY + NEZ;
@@ -384,11 +386,11 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     const int col = x0 + cx, rowy = y0 + cy;
     const size_t plane = (size_t)nz * rowsz;
     const size_t nbx = (size_t)(D.b_hi - D.b_lo) * rowsz;
-    double qc[2][NV3], Ub[2][NV3];
+    double qc[CZ][NV3], Ub[CZ][NV3];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
+    for (int hh = 0; hh < CZ; ++hh) {
         const int row = z0 + r0 + hh;
-        const bool ok = hh ? ok1 : ok0;
+        const bool ok = okc[hh];
         const bool inb = (row >= D.b_lo && row < D.b_hi);
         const Combine& cb = inb ? D.buf : D.main;
         const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
@@ -417,8 +419,13 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
 #pragma unroll
         for (int v = 0; v < NV3; ++v) e[v * st] = f[v];
     };
-    if (ok0) { put(0, cx, cy, r0, F[0]); put(1, cx, cy, r0, F[1]); put(2, cx, cy, r0, F[2]); }
-    if (ok1) { put(0, cx, cy, r0 + 1, F[3]); put(1, cx, cy, r0 + 1, F[4]); put(2, cx, cy, r0 + 1, F[5]); }
+#pragma unroll
+    for (int hh = 0; hh < CZ; ++hh) {
+        if (!okc[hh]) continue;
+        put(0, cx, cy, r0 + hh, F[3 * hh]);
+        put(1, cx, cy, r0 + hh, F[3 * hh + 1]);
+        put(2, cx, cy, r0 + hh, F[3 * hh + 2]);
+    }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int e = tid + u * NT;
@@ -431,9 +438,8 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     // ---- divergence (FP64), interface flux, source, stage combination
     const double inv_dx = A.inv_dx, inv_dy = A.inv_dy, inv_dz = D.inv_dz;
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-        const bool ok = hh ? ok1 : ok0;
-        if (!ok) continue;
+    for (int hh = 0; hh < CZ; ++hh) {
+        if (!okc[hh]) continue;
         const int zz = r0 + hh;
         const int row = z0 + zz;
         double R[NV3];
