@@ -7,13 +7,16 @@
 // eq. bulk-flux) and the stage combination of its partition (eq. MRK2 in a
 // low-storage substep form).
 //
-// Tiling: a workgroup of 256 threads owns a 32 x 16 tile of one domain.  The
-// tile's conserved state (2-cell halo) and primitives u, w, T (1-cell halo)
-// are staged in LDS; every face of the tile is computed exactly once (two
-// faces per cell plus one left column and one bottom row of edge faces) by a
-// single direction-generic face routine; the fluxes are exchanged through LDS
-// (aliasing the staged state) and each thread forms the divergence of its
-// two cells.
+// Tiling: a workgroup of 512 threads owns a 32 x 16 tile of one domain, one
+// cell per thread (other tile shapes and cells-per-thread counts are template
+// parameters).  The tile's conserved state (2-cell halo) and primitives u, w,
+// T (1-cell halo) are staged in LDS; every face of the tile is computed
+// exactly once (two faces per cell plus one left column and one bottom row of
+// edge faces) by a single direction-generic face routine; the fluxes are
+// exchanged through LDS (aliasing the staged state) and each thread forms the
+// divergence of its cells.  One cell per thread keeps the register count low
+// (74 VGPRs in FP64, 50 in FP32), so more waves hide the LDS and HBM latency
+// than with two cells per thread.
 //
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
 // stability measures and the physical-state flag.
@@ -24,9 +27,10 @@ namespace mprk {
 
 namespace {
 
-template <int X, int Z>
+template <int X, int Z, int C = 1>
 struct Shape {
-    static constexpr int TX = X, TZ = Z, NT = X * Z / 2;
+    static constexpr int CZ = C;                      // cells per thread, stacked in z
+    static constexpr int TX = X, TZ = Z, NT = X * Z / C;
     static constexpr int HX = X + 4, HZ = Z + 4;      // staged state with a 2-cell halo
     static constexpr int PX = X + 2, PZ = Z + 2;      // primitives with a 1-cell halo
     static constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
@@ -35,7 +39,7 @@ struct Shape {
     static constexpr int LOAD_RG = NT / HX;           // row groups of the loader
     static constexpr int LOAD_THREADS = LOAD_RG * HX;
     static constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG;  // rows per loader thread
-    static_assert(Z % 2 == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
+    static_assert(Z % C == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
     static_assert(NT >= 64 + X && Z <= 64, "edge faces use waves 0 and 1");
     static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
     static_assert(LOAD_RG >= 1, "loader needs a full row of threads");
@@ -248,10 +252,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     const bool has_gamma = (DOM == 0) ? (D.gamma_top && z0 + ve == nz)
                                       : (D.gamma_bot && z0 + vs == 0);
 
+    constexpr int CZ = S::CZ;
     const int c = tid % TX;
-    const int r0 = 2 * (tid / TX);
-    const bool ok0 = (c < ncols) && (r0 >= vs) && (r0 < ve);
-    const bool ok1 = (c < ncols) && (r0 + 1 >= vs) && (r0 + 1 < ve);
+    const int r0 = CZ * (tid / TX);
+    bool okc[CZ];
+#pragma unroll
+    for (int h = 0; h < CZ; ++h) okc[h] = (c < ncols) && (r0 + h >= vs) && (r0 + h < ve);
 
     // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
     // Each of LOAD_THREADS threads owns one tile column and LOAD_ROWS rows
@@ -328,25 +334,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     }
     __syncthreads();
 
-    // ---- faces.  Slots 0,1: x-faces right of the two cells; 2,3: z-faces
-    // above them; 4: the x-face left of column 0 on each computed row (wave 0)
-    // and the z-face below the first computed row (wave 1), so that no wave
-    // runs both directions.
-    const int kind2 = (z0 + r0 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
-    const int kind3 = (z0 + r0 + 1 == nz - 1) ? FACE_TOP : FACE_INTERIOR;
+    // ---- faces: the x-face right of each of the thread's cells, the z-face
+    // above it, and one edge face: the x-face left of column 0 on each
+    // computed row (wave 0) or the z-face below the first computed row
+    // (wave 1), so that no wave runs both directions.
     const bool ex_x4 = tid < TZ && tid >= vs && tid < ve;
     const int ez = tid - 64;
     const bool ex_z4 = ez >= 0 && ez < TX && ez < ncols;
     const int re = vs - 1;
     const int kind4 = (z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
-    FT F[5][NV];
-    if (ok0) face_flux<FT, 0, S>(A, D, L, c, r0, FACE_INTERIOR, F[0]);
-    if (ok1) face_flux<FT, 0, S>(A, D, L, c, r0 + 1, FACE_INTERIOR, F[1]);
-    if (ok0) face_flux<FT, 1, S>(A, D, L, c, r0, kind2, F[2]);
-    if (ok1) face_flux<FT, 1, S>(A, D, L, c, r0 + 1, kind3, F[3]);
-    if (ex_x4) face_flux<FT, 0, S>(A, D, L, -1, tid, FACE_INTERIOR, F[4]);
-    if (ex_z4) face_flux<FT, 1, S>(A, D, L, ez, re, kind4, F[4]);
+    // F[h]: x-face right of cell h; F[CZ + h]: z-face above it; F[2 CZ]: edge face.
+    FT F[2 * CZ + 1][NV];
+#pragma unroll
+    for (int h = 0; h < CZ; ++h)
+        if (okc[h]) face_flux<FT, 0, S>(A, D, L, c, r0 + h, FACE_INTERIOR, F[h]);
+#pragma unroll
+    for (int h = 0; h < CZ; ++h)
+        if (okc[h]) {
+            const int kind = (z0 + r0 + h == nz - 1) ? FACE_TOP : FACE_INTERIOR;
+            face_flux<FT, 1, S>(A, D, L, c, r0 + h, kind, F[CZ + h]);
+        }
+    if (ex_x4) face_flux<FT, 0, S>(A, D, L, -1, tid, FACE_INTERIOR, F[2 * CZ]);
+    if (ex_z4) face_flux<FT, 1, S>(A, D, L, ez, re, kind4, F[2 * CZ]);
 
     // Pointwise FP64 reads for the combination (the stage value itself when
     // the fluxes are FP32, and the substep base U); they complete while the
@@ -354,11 +364,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     const int col = x0 + c;
     const size_t plane = (size_t)nz * nx;
     const size_t nbx = (size_t)(D.b_hi - D.b_lo) * nx;
-    double qc[2][NV], Ub[2][NV];
+    double qc[CZ][NV], Ub[CZ][NV];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < CZ; ++h) {
         const int row = z0 + r0 + h;
-        const bool ok = h ? ok1 : ok0;
+        const bool ok = okc[h];
         const bool inb = (row >= D.b_lo && row < D.b_hi);
         const Combine& cb = inb ? D.buf : D.main;
         const size_t id = (size_t)row * nx + col;
@@ -392,18 +402,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         constexpr int st = (TZ + 1) * TX;
         e[0] = f[0]; e[st] = f[2]; e[2 * st] = f[1]; e[3 * st] = f[3];
     };
-    if (ok0) { put_x(c, r0, F[0]); put_z(c, r0, F[2]); }
-    if (ok1) { put_x(c, r0 + 1, F[1]); put_z(c, r0 + 1, F[3]); }
-    if (ex_x4) put_x(-1, tid, F[4]);
-    if (ex_z4) put_z(ez, re, F[4]);
+#pragma unroll
+    for (int h = 0; h < CZ; ++h)
+        if (okc[h]) { put_x(c, r0 + h, F[h]); put_z(c, r0 + h, F[CZ + h]); }
+    if (ex_x4) put_x(-1, tid, F[2 * CZ]);
+    if (ex_z4) put_z(ez, re, F[2 * CZ]);
     __syncthreads();
 
     // ---- divergence (FP64: differences of two face fluxes are exact for FP32
     // fluxes, so the exchange stays conservative), source and stage
     // combination.
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const bool ok = h ? ok1 : ok0;
+    for (int h = 0; h < CZ; ++h) {
+        const bool ok = okc[h];
         if (!ok) continue;
         const int r = r0 + h;
         const int row = z0 + r;
