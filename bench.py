@@ -67,24 +67,28 @@ def l2(dx, dzs, diffs):
     return np.sqrt(out)
 
 
-def kernel_source_hash():
+KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h"),
+                  "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h")}
+
+
+def kernel_source_hash(kernel: str = "stage_kernel"):
     h = hashlib.sha256()
-    for f in ("mprk_kernels.hip", "mprk_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_2202_11890_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(workload: str, kernel: str = "stage_kernel"):
     """HBM bytes per stage launch from a committed counter summary, if its
     kernel-source hash matches the current sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "stage_kernel_%s_hbm_traffic.json" % workload)
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except ValueError:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -507,6 +511,7 @@ def leg_3d(args, torch, dev):
     per_launch = bytes_step / (w.m * w.base)
     avg = k_ms * 1e-3 / k_n
     gbs = per_launch / avg / 1e9
+    traffic = traffic_from_profiles("large3d", "stage_kernel3")
     print("# 3d: %d steps, %.3f ms/step, %.3e cell-stage/s, stage kernel %.1f us, %.0f GB/s" % (
         K, 1e3 * t / K, cs * K / t, avg * 1e6, gbs), file=sys.stderr, flush=True)
     return {
@@ -515,7 +520,8 @@ def leg_3d(args, torch, dev):
         "dt": dt, "status": st["status"], "cell_stages_per_step": cs,
         "stage_kernel": {"avg_launch_us_bracketed": avg * 1e6,
                          "algorithmic_bytes_per_launch": int(per_launch),
-                         "achieved_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS},
+                         "achieved_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                         "traffic": None if traffic is None else round(traffic / avg / 1e9, 1)},
     }
 
 

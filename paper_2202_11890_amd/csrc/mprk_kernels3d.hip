@@ -17,10 +17,21 @@ namespace mprk {
 
 namespace {
 
+#ifndef MPRK3_PATCH_X
+#define MPRK3_PATCH_X 32
+#endif
+#ifndef MPRK3_PATCH_Y
+#define MPRK3_PATCH_Y 16
+#endif
+
 template <int X, int Y, int Z, int C>
 struct Shape3 {
     static constexpr int CZ = C;                        // cells per thread, stacked in z
     static constexpr int TX = X, TY = Y, TZ = Z, NT = X * Y * Z / C;
+    // Tile order: x-y patches of GX x GY tiles (MPRK3_PATCH_X x MPRK3_PATCH_Y
+    // cells), each walked through its z layers before the next patch.
+    static constexpr int GX = MPRK3_PATCH_X / X > 0 ? MPRK3_PATCH_X / X : 1;
+    static constexpr int GY = MPRK3_PATCH_Y / Y > 0 ? MPRK3_PATCH_Y / Y : 1;
     static constexpr int HX = X + 4, HY = Y + 4, HZ = Z + 4;
     static constexpr int PX = X + 2, PY = Y + 2, PZ = Z + 2;
     static constexpr int QPL = HY * HX;                 // staged state: one z-plane
@@ -214,6 +225,33 @@ __device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, c
     F[4] = Fn[4];
 }
 
+// Tile t of a domain's launch range -> tile coordinates.  The x-y plane is
+// cut into strips of GY tile rows and each strip into patches of GX tile
+// columns (the last strip and patch may be narrower); a patch is walked layer
+// by layer in z, x fastest, before the next patch starts.  Workgroups that run
+// at the same time on one XCD (which owns a contiguous range of t) then form a
+// compact block whose x-y halos overlap, and the layers below a block were
+// staged just before it, so the halo re-reads of the 2-cell stencil mostly
+// hit that XCD's L2 instead of HBM.  The map is a bijection onto
+// [0, tiles_x) x [0, tiles_y) x [0, tiles_z).
+template <class S>
+__device__ __forceinline__ void tile_coords3(int t, int tiles_x, int tiles_y, int tiles_z, int& tx,
+                                             int& ty, int& tz)
+{
+    const int strip = S::GY * tiles_x * tiles_z;
+    const int j = t / strip;
+    int r = t - j * strip;
+    const int wy = min(S::GY, tiles_y - j * S::GY);
+    const int patch = S::GX * wy * tiles_z;
+    const int i = r / patch;
+    r -= i * patch;
+    const int wx = min(S::GX, tiles_x - i * S::GX);
+    tz = r / (wx * wy);
+    r -= tz * (wx * wy);
+    ty = j * S::GY + r / wx;
+    tx = i * S::GX + r % wx;
+}
+
 template <int DOM, class FT>
 __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* smem)
 {
@@ -224,9 +262,8 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     const DomainArgs& O = A.d[1 - DOM];
     const int tid = threadIdx.x;
     const int nx = A.nx, ny = A.ny, nz = D.nz;
-    const int tx = tile % D.tiles_x;
-    const int ty = (tile / D.tiles_x) % D.tiles_y;
-    const int tz = tile / (D.tiles_x * D.tiles_y);
+    int tx, ty, tz;
+    tile_coords3<S>(tile, D.tiles_x, D.tiles_y, D.tiles_z, tx, ty, tz);
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = (D.row_lo / TZ + tz) * TZ;
     const int vs = max(z0, D.row_lo) - z0;
@@ -509,7 +546,7 @@ __global__ __launch_bounds__(TileOf<FT>::S::NT) void stage_kernel3(const StageAr
 {
     using S = typename TileOf<FT>::S;
     __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
-    const int b = blockIdx.x;
+    const int b = xcd_contiguous(blockIdx.x, A.nblocks);
     const int n0 = A.d[A.first].ntiles;
     const int dom = (b < n0) ? A.first : 1 - A.first;
     const int t = (b < n0) ? b : b - n0;
