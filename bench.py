@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--exec", choices=["persistent", "launch"], default="launch",
                     help="persistent: one cooperative launch per check segment; launch: one per stage")
+    ap.add_argument("--tile", choices=["32x16", "16x32", "64x8", "32x8"], default="32x16",
+                    help="2D tile shape of the headline, FP32-flux and single-rate runs")
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
@@ -133,7 +135,8 @@ def main():
     tl, tu = tl0.clone(), tu0.clone()
     cfg = mprk.config_of_workload(w)
     exec_mode = mprk.EXEC_PERSISTENT if args.exec == "persistent" else mprk.EXEC_LAUNCH
-    sol = mprk.Solver(cfg, tl, tu, exec_mode=exec_mode)
+    tile = mprk.TILE_NAMES.index(args.tile)
+    sol = mprk.Solver(cfg, tl, tu, exec_mode=exec_mode, tile=tile)
     dt = sol.stable_dt(w.cfl, w.dnum)
 
     # ---- warm-up, then restore the initial state
@@ -198,7 +201,8 @@ def main():
         bracketed = None
     avg_launch_s = gpu_ms * 1e-3 / n_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = traffic_from_profiles(args.workload) if args.exec == "launch" else None
+    # the counter summary covers the default launch configuration only
+    traffic = traffic_from_profiles(args.workload) if (args.exec == "launch" and args.tile == "32x16") else None
     if traffic is not None:
         traffic = round(traffic / avg_launch_s / 1e9, 1)   # measured HBM GB/s
     roofline = {
@@ -237,6 +241,7 @@ def main():
             "dt": dt, "cfl": w.cfl, "diffusion_number": w.dnum,
             "check_every": args.check_every,
             "exec": args.exec,
+            "tile": args.tile,
             "cell_stages_per_step": cs_step,
             "parallelism": "single GPU",
         },
@@ -253,7 +258,7 @@ def main():
     if not args.no_fp32:
         tl.copy_(tl0)
         tu.copy_(tu0)
-        f32 = mprk.Solver(mprk.config_of_workload(w, flux_bits=32), tl, tu, exec_mode=exec_mode)
+        f32 = mprk.Solver(mprk.config_of_workload(w, flux_bits=32), tl, tu, exec_mode=exec_mode, tile=tile)
         f32.run(dt, max(W, 1), check_every=0)
         tl.copy_(tl0)
         tu.copy_(tu0)
@@ -280,7 +285,7 @@ def main():
     if not args.no_sr:
         tl.copy_(tl0)
         tu.copy_(tu0)
-        sr = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu, exec_mode=exec_mode)
+        sr = mprk.Solver(mprk.config_of_workload(w, m=1), tl, tu, exec_mode=exec_mode, tile=tile)
         sr.run(dt / m, 2, check_every=0)
         tl.copy_(tl0)
         tu.copy_(tu0)
