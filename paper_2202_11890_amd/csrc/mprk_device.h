@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mprk_internal.h"
+
 namespace mprk {
 namespace {
 
@@ -11,6 +13,14 @@ __device__ __forceinline__ int wrapx(int c, int nx)
 {
     int r = c % nx;
     return r < 0 ? r + nx : r;
+}
+
+// Periodic index for c in [-n, 2n): one conditional add or subtract instead
+// of a division.  A tile's halo indices lie in [-2, n + T] for tile width T,
+// so this applies whenever n > T (callers test that uniformly).
+__device__ __forceinline__ int wrap1(int c, int n)
+{
+    return c < 0 ? c + n : (c >= n ? c - n : c);
 }
 
 // 1/sqrt(x) for positive normal x: hardware estimate refined by two Newton
@@ -69,6 +79,24 @@ template <> struct Fm<float> {
     static __device__ __forceinline__ float ws_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float ws_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
+
+// The combination of a row: the buffer's or the main one.  Both records are
+// read as (uniform) kernel arguments and selected per lane, so that no lane
+// loads through a divergent pointer into the argument segment.
+__device__ __forceinline__ Combine pick_combine(const Combine& buf, const Combine& main_, bool inb)
+{
+    const double ab = buf.alpha, am = main_.alpha;
+    const double bb = buf.beta, bm = main_.beta;
+    const double hb = buf.bh, hm = main_.bh;
+    const int mb = buf.mode, mm = main_.mode;
+    Combine c;
+    c.alpha = inb ? ab : am;
+    c.beta = inb ? bb : bm;
+    c.bh = inb ? hb : hm;
+    c.mode = inb ? mb : mm;
+    c.pad = 0;
+    return c;
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block j to XCD j % 8).
 // Give each XCD a contiguous range of the n tiles so that neighbouring tiles,

@@ -264,7 +264,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     // (stride LOAD_RG); all its global loads are issued before any is used.
     if (tid < LOAD_THREADS) {
         const int xc = tid % HX, rg = tid / HX;
-        const int col = wrapx(x0 + xc - 2, nx);
+        const int col = nx > TX ? wrap1(x0 + xc - 2, nx) : wrapx(x0 + xc - 2, nx);
         double val[LOAD_ROWS][NV];
         bool neg[LOAD_ROWS];
 #pragma unroll
@@ -304,7 +304,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     // cells next to the interface (the tiles on both sides compute the same
     // bits).
     if (has_gamma && tid < TX) {
-        const int col = wrapx(x0 + tid, nx);
+        const int col = nx > TX ? wrap1(x0 + tid, nx) : wrapx(x0 + tid, nx);
         const int own = (DOM == 0) ? nz - 1 : 0;
         const int oth = (DOM == 0) ? 0 : O.nz - 1;
         const size_t po = (size_t)nz * nx, pq = (size_t)O.nz * nx;
@@ -370,7 +370,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         const int row = z0 + r0 + h;
         const bool ok = okc[h];
         const bool inb = (row >= D.b_lo && row < D.b_hi);
-        const Combine& cb = inb ? D.buf : D.main;
+        const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)row * nx + col;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -441,7 +441,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         R[3] += qc[h][2] * A.gravity;
 
         const bool inb = (row >= D.b_lo && row < D.b_hi);
-        const Combine& cb = inb ? D.buf : D.main;
+        const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)row * nx + col;
         if (cb.mode == MODE_RHS) {
 #pragma unroll

@@ -303,7 +303,9 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
             if (idx < NCELL) {
                 const int zz = idx / (HY * HX), rem = idx - zz * (HY * HX);
                 const int yy = rem / HX, xx = rem - yy * HX;
-                const int col = wrapx(x0 + xx - 2, nx), rowy = wrapx(y0 + yy - 2, ny);
+                const bool near = nx > TX && ny > TY;
+                const int col = near ? wrap1(x0 + xx - 2, nx) : wrapx(x0 + xx - 2, nx);
+                const int rowy = near ? wrap1(y0 + yy - 2, ny) : wrapx(y0 + yy - 2, ny);
                 int pl = z0 + zz - 2;
                 if (pl < 0) { pl = 0; neg[u] = true; }
                 else if (pl >= nz) { pl = nz - 1; neg[u] = true; }
@@ -336,7 +338,9 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     if (has_gamma) {
         for (int c = tid; c < TX * TY; c += NT) {
             const int xx = c % TX, yy = c / TX;
-            const int col = wrapx(x0 + xx, nx), rowy = wrapx(y0 + yy, ny);
+            const bool near = nx > TX && ny > TY;
+            const int col = near ? wrap1(x0 + xx, nx) : wrapx(x0 + xx, nx);
+            const int rowy = near ? wrap1(y0 + yy, ny) : wrapx(y0 + yy, ny);
             const int own = (DOM == 0) ? nz - 1 : 0;
             const int oth = (DOM == 0) ? 0 : O.nz - 1;
             const size_t po = (size_t)nz * rowsz, pq = (size_t)O.nz * rowsz;
@@ -429,7 +433,7 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
         const int row = z0 + r0 + hh;
         const bool ok = okc[hh];
         const bool inb = (row >= D.b_lo && row < D.b_hi);
-        const Combine& cb = inb ? D.buf : D.main;
+        const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
 #pragma unroll
         for (int v = 0; v < NV3; ++v) {
@@ -503,7 +507,7 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
         R[4] += qc[hh][3] * A.gravity;
 
         const bool inb = (row >= D.b_lo && row < D.b_hi);
-        const Combine& cb = inb ? D.buf : D.main;
+        const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
         if (cb.mode == MODE_RHS) {
 #pragma unroll
