@@ -50,7 +50,7 @@ struct Shape3 {
 #define MPRK3_CZ32 1
 #endif
 using T32 = Shape3<16, 8, 4, MPRK3_CZ32>;   // FP32 fluxes: 58.8 KB LDS
-using T64 = Shape3<8, 4, 4, 1>;             // FP64 fluxes: 43.0 KB LDS, 128 threads
+using T64 = Shape3<16, 4, 4, 1>;            // FP64 fluxes: 73.5 KB LDS, 256 threads
 
 template <class FT> struct TileOf;
 template <> struct TileOf<float> { using S = T32; };
