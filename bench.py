@@ -352,6 +352,24 @@ def main():
         print("# cpu oracle: %d steps in %.1f s on %d threads" % (n, el, oracle.threads()),
               file=sys.stderr, flush=True)
 
+    # The paper's own figures (CPU wall clocks, converted to cell-stage
+    # updates/s with the same counting): context, not a like-for-like target.
+    out["paper_context"] = {
+        "note": "CPU wall-clock figures of the paper converted to cell-stage updates/s "
+                "(s*N_S + m*s*(N_B + N_F) per MPRK step); different problems and code, precision not stated",
+        "rows": [
+            {"workload": "2D thermal convection, MPRK2 m=2 (Table 5)", "mprk": 2.36e6, "single_rate": 2.47e6,
+             "hardware": "not stated"},
+            {"workload": "2D thermal convection, MPRK2 m=4 (Table 7)", "mprk": 2.23e6, "single_rate": 1.88e6,
+             "hardware": "not stated"},
+            {"workload": "weak scaling, wind-driven flow, 32768 cores (Table 8)", "mprk": 1.46e9,
+             "single_rate": 3.66e9, "hardware": "Theta: Cray XC40, Xeon Phi 7230 (64 cores per node)"},
+            {"workload": "weak scaling, thermal bubble, 32768 cores (Table 9)", "mprk": 2.31e9,
+             "single_rate": 4.13e9, "hardware": "Theta: Cray XC40, Xeon Phi 7230 (64 cores per node)"},
+        ],
+        "unit": "cell-stage updates/s",
+    }
+
     if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(args, torch, dev)
     if not args.no_serving:
