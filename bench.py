@@ -577,6 +577,8 @@ def serving_leg(args, torch, dev):
     t0 = time.perf_counter()
     res = srv.run(reqs)
     sat = serving.summarize(res, cs, time.perf_counter() - t0)
+    sat["host_seconds"] = dict(srv.seconds)
+    sat["batch_rebuilds"] = srv.rebuilds
     capacity = sat["requests"] / sat["makespan_s"]
     rate = args.serving_load * capacity
     reqs, cs = make(rate, 12)
@@ -587,9 +589,13 @@ def serving_leg(args, torch, dev):
     load["arrival_rate_per_s"] = rate
     load["mean_active"] = float(np.mean([a for _, a, _ in srv.log])) if srv.log else 0.0
     load["batch_rebuilds"] = srv.rebuilds
+    load["host_seconds"] = dict(srv.seconds)
     print("# serving: capacity %.1f req/s (%.3e cell-stage/s); at %.1f req/s p50 %.3f s p99 %.3f s" % (
         capacity, sat["cell_stage_updates_per_s"], rate, load["latency_s"]["p50"],
         load["latency_s"]["p99"]), file=sys.stderr, flush=True)
+    print("# serving saturated: %d rebuilds, seconds %s" % (
+        sat["batch_rebuilds"], {k: round(v, 3) for k, v in sat["host_seconds"].items()}),
+        file=sys.stderr, flush=True)
     return {
         "workload": "%d requests, nx log-uniform 64..1024 (nz = nx/2), 50..500 slow steps, m in {2,4}, "
                     "MPRK2, FP64; budget %d GiB, 64 slots, 10-step chunks" % (n, budget >> 30),

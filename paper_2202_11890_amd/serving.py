@@ -4,8 +4,9 @@ Requests (a two-domain problem, its initial state and a number of slow
 steps) arrive over time.  The server keeps every admitted request's state
 resident in device memory and advances all of them together as one batch
 (``mprk_batch_*``), a chunk of slow steps at a time.  Between chunks,
-finished requests leave (their state is copied back and their memory
-released) and requests that have arrived are admitted while the device
+finished requests leave (their state is copied to pinned host memory on a
+copy stream while the next chunk runs, and their memory is released when the
+copy completes) and requests that have arrived are admitted while the device
 memory budget (state + workspace share, ``mprk_batch_workspace_bytes``) and
 the slot count allow, so new work joins work already on the device.
 
@@ -103,23 +104,47 @@ class Server:
         self.used = 0
         self.rebuilds = 0
         self.log = []                # (time, active count, bytes held) after each chunk
+        # host seconds spent admitting (copies in), rebuilding the batch (with
+        # the step rule of new requests), running chunks and retiring (copies out)
+        self.seconds = {"admit": 0.0, "rebuild": 0.0, "run": 0.0, "retire": 0.0}
+        # finished requests whose states are on their way to pinned host
+        # memory (a copy stream overlaps the copies with the next chunk)
+        self.outgoing = []
+        self.copy_stream = None      # created at the first retirement
 
     # -- helpers -----------------------------------------------------------
-    def _stable_dt(self, cfg, ql, qu) -> float:
-        b = mprk.Batch([(cfg, ql, qu, 1.0)])
-        dt = b.stable_dts(self.cr, self.dn)[0]
-        b.close()
-        return dt
-
     def _rebuild(self):
         if self.batch is not None:
             self.batch.close()
             self.batch = None
         if self.active:
-            self.batch = mprk.Batch([(a.req.cfg, a.ql, a.qu, a.dt) for a in self.active],
-                                    exec_mode=self.exec_mode, tile=self.tile)
+            self.batch = mprk.Batch([(a.req.cfg, a.ql, a.qu, a.dt if a.dt is not None else 1.0)
+                                     for a in self.active], exec_mode=self.exec_mode, tile=self.tile)
             self.rebuilds += 1
+            # Step rule for requests admitted without one, from their initial
+            # state: one batched reduction for all of them (each member's
+            # reduction is its own, so the step is the one it would get alone).
+            if any(a.dt is None for a in self.active):
+                dts = self.batch.stable_dts(self.cr, self.dn)
+                for i, a in enumerate(self.active):
+                    if a.dt is None:
+                        a.dt = dts[i]
+                        self.batch.set_dt(i, a.dt)
         self.dirty = False
+
+    def _drain(self, results, t0, block=False):
+        """Turn finished copies into results (all of them when block)."""
+        keep = []
+        for a, hl, hu, ev, status in self.outgoing:
+            if block:
+                ev.synchronize()
+            if block or ev.query():
+                results.append(Result(a.req.rid, hl.numpy(), hu.numpy(), a.dt, a.done, a.req.arrival,
+                                      a.admitted, self.clock() - t0, status))
+                self.used -= a.bytes
+            else:
+                keep.append((a, hl, hu, ev, status))
+        self.outgoing = keep
 
     # -- main loop ---------------------------------------------------------
     def run(self, requests: List[Request]) -> List[Result]:
@@ -130,9 +155,11 @@ class Server:
                 raise ValueError("request %d needs more memory than the whole budget" % r.rid)
         results: List[Result] = []
         t0 = self.clock()
-        while pending or self.active:
+        while pending or self.active or self.outgoing:
+            self._drain(results, t0)
             now = self.clock() - t0
             # admit, in arrival order, while memory and slots allow
+            ta = self.clock()
             while pending and pending[0].arrival <= now and len(self.active) < self.max_slots:
                 r = pending[0]
                 need = footprint(r.cfg)
@@ -141,40 +168,63 @@ class Server:
                 pending.pop(0)
                 ql = torch.from_numpy(np.ascontiguousarray(r.q_lower)).to(self.device)
                 qu = torch.from_numpy(np.ascontiguousarray(r.q_upper)).to(self.device)
-                dt = r.dt if r.dt is not None else self._stable_dt(r.cfg, ql, qu)
-                self.active.append(_Active(r, ql, qu, dt, self.clock() - t0, need))
+                # dt None: set at the next rebuild, from this initial state
+                self.active.append(_Active(r, ql, qu, r.dt, self.clock() - t0, need))
                 self.used += need
                 self.dirty = True
+            self.seconds["admit"] += self.clock() - ta
             if not self.active:
+                if self.outgoing:
+                    self._drain(results, t0, block=True)
+                    continue
                 # idle until the next arrival
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
                     time.sleep(wait)
                 continue
             if self.dirty or self.batch is None:
+                tb = self.clock()
                 self._rebuild()
+                self.seconds["rebuild"] += self.clock() - tb
             # advance everyone by a chunk, or less so that the first request
             # to finish ends exactly at its step count
             k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
+            tr = self.clock()
             rc, stats = self.batch.run_status(k)
+            self.seconds["run"] += self.clock() - tr
             if rc not in (mprk.OK, mprk.ENONFINITE):
                 raise mprk.MprkError(rc, "mprk_batch_run")
             for a in self.active:
                 a.done += k
-            # retire finished requests, and requests whose state went bad
+            # retire finished requests, and requests whose state went bad:
+            # their states are copied to pinned host memory on the copy
+            # stream, after this chunk, while the next chunk computes; their
+            # device memory counts against the budget until the copy is done
+            tr = self.clock()
             keep = []
-            now = self.clock() - t0
+            synced = False
             for a, st in zip(self.active, stats):
                 if a.done >= a.req.steps or st["status"]:
-                    results.append(Result(a.req.rid, a.ql.cpu().numpy(), a.qu.cpu().numpy(), a.dt,
-                                          a.done, a.req.arrival, a.admitted, now, st["status"]))
-                    self.used -= a.bytes
+                    if not synced:
+                        if self.copy_stream is None:
+                            self.copy_stream = torch.cuda.Stream(self.device)
+                        self.copy_stream.wait_stream(torch.cuda.current_stream(self.device))
+                        synced = True
+                    hl = torch.empty(tuple(a.ql.shape), dtype=a.ql.dtype, pin_memory=True)
+                    hu = torch.empty(tuple(a.qu.shape), dtype=a.qu.dtype, pin_memory=True)
+                    with torch.cuda.stream(self.copy_stream):
+                        hl.copy_(a.ql, non_blocking=True)
+                        hu.copy_(a.qu, non_blocking=True)
+                        ev = torch.cuda.Event()
+                        ev.record(self.copy_stream)
+                    self.outgoing.append((a, hl, hu, ev, st["status"]))
                 else:
                     keep.append(a)
             if len(keep) != len(self.active):
                 self.active = keep
                 self.dirty = True
-            self.log.append((now, len(self.active), self.used))
+            self.seconds["retire"] += self.clock() - tr
+            self.log.append((self.clock() - t0, len(self.active), self.used))
         if self.batch is not None:
             self.batch.close()
             self.batch = None
