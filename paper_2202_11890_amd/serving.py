@@ -132,13 +132,32 @@ class Server:
                         self.batch.set_dt(i, a.dt)
         self.dirty = False
 
+    def _copy_out(self, a, first):
+        """Start copying a finished request's state to host memory: (lower,
+        upper, completion event, or None when the copy is already done)."""
+        torch = self.torch
+        if torch.device(self.device).type != "cuda":
+            return a.ql.clone(), a.qu.clone(), None
+        if first:
+            if self.copy_stream is None:
+                self.copy_stream = torch.cuda.Stream(self.device)
+            self.copy_stream.wait_stream(torch.cuda.current_stream(self.device))
+        hl = torch.empty(tuple(a.ql.shape), dtype=a.ql.dtype, pin_memory=True)
+        hu = torch.empty(tuple(a.qu.shape), dtype=a.qu.dtype, pin_memory=True)
+        with torch.cuda.stream(self.copy_stream):
+            hl.copy_(a.ql, non_blocking=True)
+            hu.copy_(a.qu, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        return hl, hu, ev
+
     def _drain(self, results, t0, block=False):
         """Turn finished copies into results (all of them when block)."""
         keep = []
         for a, hl, hu, ev, status in self.outgoing:
-            if block:
+            if block and ev is not None:
                 ev.synchronize()
-            if block or ev.query():
+            if block or ev is None or ev.query():
                 results.append(Result(a.req.rid, hl.numpy(), hu.numpy(), a.dt, a.done, a.req.arrival,
                                       a.admitted, self.clock() - t0, status))
                 self.used -= a.bytes
@@ -177,6 +196,8 @@ class Server:
                 if self.outgoing:
                     self._drain(results, t0, block=True)
                     continue
+                if not pending:
+                    break
                 # idle until the next arrival
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -202,21 +223,11 @@ class Server:
             # device memory counts against the budget until the copy is done
             tr = self.clock()
             keep = []
-            synced = False
+            first = True
             for a, st in zip(self.active, stats):
                 if a.done >= a.req.steps or st["status"]:
-                    if not synced:
-                        if self.copy_stream is None:
-                            self.copy_stream = torch.cuda.Stream(self.device)
-                        self.copy_stream.wait_stream(torch.cuda.current_stream(self.device))
-                        synced = True
-                    hl = torch.empty(tuple(a.ql.shape), dtype=a.ql.dtype, pin_memory=True)
-                    hu = torch.empty(tuple(a.qu.shape), dtype=a.qu.dtype, pin_memory=True)
-                    with torch.cuda.stream(self.copy_stream):
-                        hl.copy_(a.ql, non_blocking=True)
-                        hu.copy_(a.qu, non_blocking=True)
-                        ev = torch.cuda.Event()
-                        ev.record(self.copy_stream)
+                    hl, hu, ev = self._copy_out(a, first)
+                    first = False
                     self.outgoing.append((a, hl, hu, ev, st["status"]))
                 else:
                     keep.append(a)
