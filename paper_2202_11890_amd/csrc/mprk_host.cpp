@@ -48,6 +48,14 @@ int shu_osher(int base, double* alpha)
 
 int tiles_of(int n, int t) { return (n + t - 1) / t; }
 
+// Default 2D tile shape per flux precision (measured on the 1024x512
+// workload: 32x16 fastest with FP64 fluxes, 32x8 with FP32 fluxes, which need
+// half the LDS per tile).  3D contexts ignore the 2D shape.
+int default_shape(const mprk_config& c)
+{
+    return (c.dim == 2 && c.flux_bits == 32) ? TILE_32x8 : TILE_32x16;
+}
+
 int nv_of(const mprk_config& c) { return c.dim == 3 ? NV3 : NV; }
 
 // Fixed tiles of both domains for a tile shape (3D: the 3D kernel's tile).
@@ -1183,6 +1191,7 @@ int mprk_create(const mprk_config* cfg, double* q_lower, double* q_upper, void* 
     c->lay = L;
     c->mb.init(*cfg, L.core, q_lower, q_upper, (char*)workspace);
     c->stream = (hipStream_t)hip_stream;
+    c->shape = default_shape(*cfg);
     *out = c;
     return MPRK_OK;
 }
@@ -1365,6 +1374,7 @@ int mprk_batch_create(const mprk_member* members, int32_t n, void* workspace, si
     b->ws = (char*)workspace;
     b->stream = (hipStream_t)hip_stream;
     b->flux32 = members[0].cfg.flux_bits == 32;
+    b->shape = default_shape(members[0].cfg);
     b->mb.resize(n);
     b->dt.resize(n);
     b->rec0.resize(n);
