@@ -64,7 +64,7 @@ enum mprk_status {
     MPRK_EWORKSPACE = -3,   /* workspace missing, too small or not 256-B aligned     */
     MPRK_EHIP = -4,         /* a HIP runtime call or kernel launch failed            */
     MPRK_ENONFINITE = -5,   /* non-finite value, rho <= 0 or p <= 0 detected         */
-    MPRK_EUNSUPPORTED = -6, /* valid request this build or device does not support   */
+    MPRK_EUNSUPPORTED = -6, /* valid request the library or device does not support  */
     MPRK_ETIMEOUT = -7      /* persistent execution: a tile waited over its time limit
                                for a neighbour (the run was aborted; the state is not
                                a completed step)                                      */

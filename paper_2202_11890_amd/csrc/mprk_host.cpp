@@ -1068,7 +1068,7 @@ const char* mprk_strerror(int code)
     case MPRK_EWORKSPACE: return "workspace missing, too small or misaligned";
     case MPRK_EHIP: return "HIP runtime error";
     case MPRK_ENONFINITE: return "non-finite or non-physical state";
-    case MPRK_EUNSUPPORTED: return "not supported by this build or device";
+    case MPRK_EUNSUPPORTED: return "not supported by the library or device";
     case MPRK_ETIMEOUT: return "a persistent-kernel wait timed out (run aborted)";
     default: return "unknown status";
     }
