@@ -580,6 +580,15 @@ namespace {
 
 // ---- single context ------------------------------------------------------
 
+// Stage records of a single context: device-scope result stores in 2D (see
+// st_dev; batches and 3D keep ordinary stores, which measured faster there).
+StageArgs ctx_stage_args(const mprk_ctx* c, double dt, int k, int j)
+{
+    StageArgs a = stage_args(c->mb, dt, k, j, c->shape);
+    a.dev_stores = c->mb.cfg.dim == 2 ? 1 : 0;
+    return a;
+}
+
 hipError_t launch_any(const mprk_ctx* c, const StageArgs& a)
 {
     if (c->mb.cfg.dim == 3) return launch_stage3(a, c->stream);
@@ -611,7 +620,7 @@ int step_launches(mprk_ctx* c, double dt)
     const int s = c->mb.lay.s, m = c->mb.cfg.m;
     for (int k = 1; k <= m; ++k) {
         for (int j = 1; j <= s; ++j) {
-            int rc = launch(c, stage_args(c->mb, dt, k, j, c->shape));
+            int rc = launch(c, ctx_stage_args(c, dt, k, j));
             if (rc != MPRK_OK) return rc;
         }
     }
@@ -626,7 +635,7 @@ int ctx_graph(mprk_ctx* c, double dt)
     const int s = c->mb.lay.s, m = c->mb.cfg.m, ms = m * s;
     c->g_args.clear();
     for (int k = 1; k <= m; ++k)
-        for (int j = 1; j <= s; ++j) c->g_args.push_back(stage_args(c->mb, dt, k, j, c->shape));
+        for (int j = 1; j <= s; ++j) c->g_args.push_back(ctx_stage_args(c, dt, k, j));
     c->g_ptrs.resize(ms);
     if (!c->graph.begin()) return MPRK_EHIP;
     const KernelRef kr = c->mb.cfg.dim == 3 ? stage3_kernel_ref(c->mb.cfg.flux_bits == 32)
@@ -677,7 +686,7 @@ int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
         std::vector<StageArgs>& tab = c->h_tab;
         tab.clear();
         for (int k = 1; k <= g.m; ++k)
-            for (int j = 1; j <= c->mb.lay.s; ++j) tab.push_back(stage_args(c->mb, dt, k, j, c->shape));
+            for (int j = 1; j <= c->mb.lay.s; ++j) tab.push_back(ctx_stage_args(c, dt, k, j));
         if (hipMemcpyAsync(ws + c->lay.off_ptab, tab.data(), tab.size() * sizeof(StageArgs),
                            hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return MPRK_EHIP;

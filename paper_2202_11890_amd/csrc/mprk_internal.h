@@ -92,6 +92,7 @@ struct StageArgs {
     int32_t nblocks;         // d[0].ntiles + d[1].ntiles
     int32_t first;           // domain whose tiles take the first blocks
     int32_t flux32;          // 1: face fluxes in FP32 (state, stage sums, interface flux FP64)
+    int32_t dev_stores;      // 1: stage results stored with device coherence (see st_dev)
     double dx, inv_dx;
     double gamma, gm1, gravity;
     double bu, bT;           // bulk coefficients of the interface flux

@@ -445,11 +445,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         const size_t id = (size_t)row * nx + col;
         if (cb.mode == MODE_RHS) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) D.out[v * plane + id] = R[v];
+            for (int v = 0; v < NV; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], R[v]);
         } else if (cb.alpha == 0.0) {
             // First stage of a base step: Qin is the base U itself.
 #pragma unroll
-            for (int v = 0; v < NV; ++v) D.out[v * plane + id] = qc[h][v] + cb.bh * R[v];
+            for (int v = 0; v < NV; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], qc[h][v] + cb.bh * R[v]);
         } else {
             // Increment form of alpha U + beta (Qin + h R): U + beta (Qin - U)
             // + beta h R, exact when R = 0 and Qin = U.
@@ -458,28 +458,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
             for (int v = 0; v < NV; ++v) inc[v] = cb.beta * (qc[h][v] - Ub[h][v]) + cb.bh * R[v];
             if (cb.mode == MODE_STAGE) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) D.out[v * plane + id] = Ub[h][v] + inc[v];
+                for (int v = 0; v < NV; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], Ub[h][v] + inc[v]);
             } else {
                 // Buffer: accumulate the increments of the m trial steps and
                 // add their mean to q^B_n after the last one.
                 const size_t ia = (size_t)(row - D.b_lo) * nx + col;
                 if (cb.mode == MODE_ACC_FIRST) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) D.acc[v * nbx + ia] = inc[v];
+                    for (int v = 0; v < NV; ++v) st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], inc[v]);
                 } else if (cb.mode == MODE_ACC_ADD) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) D.acc[v * nbx + ia] += inc[v];
+                    for (int v = 0; v < NV; ++v) st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], D.acc[v * nbx + ia] + inc[v]);
                 } else {
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        D.out[v * plane + id] = Ub[h][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m;
+                        st_dev(A.dev_stores != 0, &D.out[v * plane + id], Ub[h][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m);
                 }
             }
         }
         if (D.ret_out && row >= D.ret_lo && row < D.ret_lo + 2) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * nx + col] = qc[h][v];
+                st_dev(A.dev_stores != 0, &D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * nx + col], qc[h][v]);
         }
     }
 }

@@ -511,36 +511,36 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
         const size_t id = (size_t)row * rowsz + (size_t)rowy * nx + col;
         if (cb.mode == MODE_RHS) {
 #pragma unroll
-            for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = R[v];
+            for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], R[v]);
         } else if (cb.alpha == 0.0) {
 #pragma unroll
-            for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = qc[hh][v] + cb.bh * R[v];
+            for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], qc[hh][v] + cb.bh * R[v]);
         } else {
             double inc[NV3];
 #pragma unroll
             for (int v = 0; v < NV3; ++v) inc[v] = cb.beta * (qc[hh][v] - Ub[hh][v]) + cb.bh * R[v];
             if (cb.mode == MODE_STAGE) {
 #pragma unroll
-                for (int v = 0; v < NV3; ++v) D.out[v * plane + id] = Ub[hh][v] + inc[v];
+                for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], Ub[hh][v] + inc[v]);
             } else {
                 const size_t ia = (size_t)(row - D.b_lo) * rowsz + (size_t)rowy * nx + col;
                 if (cb.mode == MODE_ACC_FIRST) {
 #pragma unroll
-                    for (int v = 0; v < NV3; ++v) D.acc[v * nbx + ia] = inc[v];
+                    for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], inc[v]);
                 } else if (cb.mode == MODE_ACC_ADD) {
 #pragma unroll
-                    for (int v = 0; v < NV3; ++v) D.acc[v * nbx + ia] += inc[v];
+                    for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], D.acc[v * nbx + ia] + inc[v]);
                 } else {
 #pragma unroll
                     for (int v = 0; v < NV3; ++v)
-                        D.out[v * plane + id] = Ub[hh][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m;
+                        st_dev(A.dev_stores != 0, &D.out[v * plane + id], Ub[hh][v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m);
                 }
             }
         }
         if (D.ret_out && row >= D.ret_lo && row < D.ret_lo + 2) {
 #pragma unroll
             for (int v = 0; v < NV3; ++v)
-                D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * rowsz + (size_t)rowy * nx + col] = qc[hh][v];
+                st_dev(A.dev_stores != 0, &D.ret_out[(size_t)(v * 2 + row - D.ret_lo) * rowsz + (size_t)rowy * nx + col], qc[hh][v]);
         }
     }
 }
