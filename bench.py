@@ -57,6 +57,8 @@ def parse():
                     help="Poisson arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--ensemble-steps", type=int, default=None, help="default: the members' 500")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the reference-solution errors")
+    ap.add_argument("--no-buffer6", action="store_true",
+                    help="skip the run with 6 buffer rows (the exactly conservative width for SSP-RK3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -96,6 +98,20 @@ def traffic_from_profiles(workload: str, kernel: str = "stage_kernel"):
     if d.get("kernel_source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def drift(s0, s1, ie=3):
+    """Change of the conserved totals between two stats: mass of each domain
+    relative to its own mass, total x-momentum relative to the total mass,
+    total energy relative to itself (Section 5.1's conservation check)."""
+    a0 = np.array([s0["totals_lower"], s0["totals_upper"]])
+    a1 = np.array([s1["totals_lower"], s1["totals_upper"]])
+    return {
+        "mass_lower": float(abs(a1[0, 0] - a0[0, 0]) / a0[0, 0]),
+        "mass_upper": float(abs(a1[1, 0] - a0[1, 0]) / a0[1, 0]),
+        "x_momentum": float(abs(a1[:, 1].sum() - a0[:, 1].sum()) / a0[:, 0].sum()),
+        "energy": float(abs(a1[:, ie].sum() - a0[:, ie].sum()) / a0[:, ie].sum()),
+    }
 
 
 def main():
@@ -148,6 +164,8 @@ def main():
     tu.copy_(tu0)
     torch.cuda.synchronize()
 
+    tot0 = sol.diagnostics()            # conserved totals at t = 0 (outside the timed region)
+
     # ---- timed region: K slow steps (wall clock and events on the stream)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -164,6 +182,7 @@ def main():
     mprk_final = (tl.cpu().numpy(), tu.cpu().numpy())
     print("# mprk: %d steps in %.3f s (%.1f us/step), status %d" %
           (K, t_mprk, 1e6 * t_mprk / K, st["status"]), file=sys.stderr, flush=True)
+    conservation = {"n_buffer_%d" % w.n_buffer: drift(tot0, st)}
 
     # ---- per-step latency (events on the solver's stream)
     lat = []
@@ -327,6 +346,30 @@ def main():
                 "l2_single_rate": [float(x) for x in e_sr],
                 "components": ["rho", "rho u", "rho w", "rho E"],
             }
+
+    # ---- the same run with 6 buffer rows (>= 2s - 1: exactly conservative)
+    if not args.no_buffer6:
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        nb6 = mprk.Solver(mprk.config_of_workload(w, n_buffer=6), tl, tu, exec_mode=exec_mode, tile=tile)
+        nb6.run(dt, max(W, 1), check_every=0)
+        tl.copy_(tl0)
+        tu.copy_(tu0)
+        t6 = nb6.diagnostics()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st6 = nb6.run(dt, K, check_every=args.check_every)
+        torch.cuda.synchronize()
+        t_6 = time.perf_counter() - t0
+        nb6.close()
+        nF6, nB6, nS6 = costmodel.partition_counts(w.nx, nzf, nzs, 6)
+        cs6 = costmodel.mprk_cell_stages(nF6, nB6, nS6, m, s)
+        d6 = drift(t6, st6)
+        d6.update({"value": cs6 * K / t_6, "ms_per_step": 1e3 * t_6 / K, "status": st6["status"]})
+        conservation["n_buffer_6"] = d6
+        print("# 6 buffer rows: %.1f us/step, mass drift %.1e / %.1e, energy drift %.1e" % (
+            1e6 * t_6 / K, d6["mass_lower"], d6["mass_upper"], d6["energy"]), file=sys.stderr, flush=True)
+    out["conservation"] = conservation
 
     # ---- CPU oracle on a bounded sample (test infrastructure, host cores)
     if not args.no_cpu:
