@@ -395,6 +395,24 @@ def main():
         }
         print("# cpu oracle: %d steps in %.1f s on %d threads" % (n, el, oracle.threads()),
               file=sys.stderr, flush=True)
+        # the same oracle on one thread, on a shorter sample
+        nthr = oracle.threads()
+        oracle.set_threads(1)
+        a, b = ql0.copy(), qu0.copy()
+        n1 = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.mprk_step(pb, s, m, dt, a, b)
+            n1 += 1
+            el1 = time.perf_counter() - t0
+            if el1 >= args.cpu_seconds / 2 or n1 >= K:
+                break
+        oracle.set_threads(nthr)
+        out["cpu_baseline"]["single_thread"] = {
+            "value": cs_step * n1 / el1, "cores": 1,
+            "sample": "%d slow steps from the initial state (%.1f s)" % (n1, el1),
+        }
+        print("# cpu oracle, one thread: %d steps in %.1f s" % (n1, el1), file=sys.stderr, flush=True)
 
     # The paper's own figures (CPU wall clocks, converted to cell-stage
     # updates/s with the same counting): context, not a like-for-like target.
