@@ -20,9 +20,9 @@ __device__ __forceinline__ int wrapx(int c, int nx)
 // at device scope, i.e. a plain vector store with the device-coherence bit;
 // otherwise an ordinary store.  The stored bits are the same.  Measured per
 // step: a single 2D context (1024 x 512 workload) runs 6% (FP64 fluxes) to 8%
-// (FP32 fluxes) faster with device-scope stores, while the batched 2D
-// ensemble runs 13% slower and the 3D workload 3% slower, so the host enables
-// them for single 2D contexts only.  Non-temporal stores were slower still.
+// (FP32 fluxes) faster with device-scope stores, while small contexts, the
+// batched 2D ensemble and the 3D workload run slower with them, so the host
+// chooses per launch record.  Non-temporal stores were slower still.
 __device__ __forceinline__ void st_dev(bool dev, double* p, double x)
 {
     if (dev) __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
