@@ -74,8 +74,8 @@ def l2(dx, dzs, diffs):
     return np.sqrt(out)
 
 
-KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h"),
-                  "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h")}
+KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h", "mprk_device.h"),
+                  "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h", "mprk_device.h")}
 
 
 def kernel_source_hash(kernel: str = "stage_kernel"):
