@@ -238,3 +238,15 @@ def test_workspace_bytes_3d():
     # batches hold 2D problems only
     m = mprk.mprk_member(cfg, 1 << 20, 1 << 28, 0.01)
     assert mprk.mprk_batch_validate([m])[0] == mprk.EUNSUPPORTED
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
