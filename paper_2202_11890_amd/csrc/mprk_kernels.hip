@@ -259,6 +259,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
 #pragma unroll
     for (int h = 0; h < CZ; ++h) okc[h] = (c < ncols) && (r0 + h >= vs) && (r0 + h < ve);
 
+    // Waves raise their issue priority while they issue the tile's global
+    // loads (staging, and later the pointwise reads), so that the loads of
+    // a workgroup leave early while the other workgroups of the CU compute
+    // (2% per step on the 1024 x 512 workload).
+    __builtin_amdgcn_s_setprio(2);
+
     // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
     // Each of LOAD_THREADS threads owns one tile column and LOAD_ROWS rows
     // (stride LOAD_RG); all its global loads are issued before any is used.
@@ -321,6 +327,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     }
     __syncthreads();
 
+    __builtin_amdgcn_s_setprio(0);
+
     // ---- primitives on the tile plus a 1-cell ring
     for (int idx = tid; idx < PZ * PX; idx += NT) {
         const int pr = idx / PX, pc = idx - pr * PX;
@@ -358,6 +366,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     if (ex_x4) face_flux<FT, 0, S>(A, D, L, -1, tid, FACE_INTERIOR, F[2 * CZ]);
     if (ex_z4) face_flux<FT, 1, S>(A, D, L, ez, re, kind4, F[2 * CZ]);
 
+    __builtin_amdgcn_s_setprio(2);
     // Pointwise FP64 reads for the combination (the stage value itself when
     // the fluxes are FP32, and the substep base U); they complete while the
     // fluxes are exchanged.
@@ -389,6 +398,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
             for (int v = 0; v < NV; ++v) Ub[h][v] = D.base[v * plane + id];
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();   // all LDS reads of the staged state are done
 
     // Fluxes back from the face-normal frame to (rho, rho u, rho w, rho E).
