@@ -225,15 +225,14 @@ def main():
     achieved = bytes_per_launch / avg_launch_s / 1e9
     # the counter summary covers the default launch configuration only
     traffic = traffic_from_profiles(args.workload) if (args.exec == "launch" and args.tile in (None, "32x16")) else None
-    if traffic is not None:
-        traffic = round(traffic / avg_launch_s / 1e9, 1)   # measured HBM GB/s
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
+        "traffic": traffic,                 # counter HBM bytes per launch
+        "traffic_gbs": None if traffic is None else round(traffic / avg_launch_s / 1e9, 1),
         "kernel": kernel_name,
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
         "avg_launch_us_bracketed": bracketed,
@@ -609,7 +608,8 @@ def leg_3d(args, torch, dev):
         "stage_kernel": {"avg_launch_us_bracketed": avg * 1e6,
                          "algorithmic_bytes_per_launch": int(per_launch),
                          "achieved_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
-                         "traffic": None if traffic is None else round(traffic / avg / 1e9, 1)},
+                         "traffic": traffic,
+                         "traffic_gbs": None if traffic is None else round(traffic / avg / 1e9, 1)},
     }
 
 

@@ -10,11 +10,11 @@ namespace mprk {
 constexpr int NV = 4;          // 2D: (rho, rho u, rho w, rho E)
 constexpr int NV3 = 5;         // 3D: (rho, rho u, rho v, rho w, rho E)
 
-// Stage tile shapes: TX columns x TZ rows of cells per workgroup of
-// TX*TZ/2 threads; each thread owns a vertical pair of cells.  The conserved
-// state is staged with a 2-cell halo (reconstruction stencil), primitives
-// with a 1-cell halo.  Every kernel is instantiated for each shape; the host
-// picks one per context (default 32 x 16, or the autotuner's choice).
+// Stage tile shapes: TX columns x TZ rows of cells per workgroup of TX*TZ
+// threads, one cell per thread.  The conserved state is staged with a 2-cell
+// halo (reconstruction stencil), primitives with a 1-cell halo.  Every kernel
+// is instantiated for each shape; the host picks one per context (32 x 16
+// with FP64 fluxes, 32 x 8 with FP32 fluxes, or the autotuner's choice).
 enum TileShape : int32_t {
     TILE_32x16 = 0,
     TILE_16x32 = 1,
@@ -31,13 +31,13 @@ struct TileDims3 {
     int tx, ty, tz, nt;
 };
 
-inline TileDims tile_dims(int shape)
+constexpr TileDims tile_dims(int shape)
 {
     switch (shape) {
-    case TILE_16x32: return {16, 32, 256};
-    case TILE_64x8: return {64, 8, 256};
-    case TILE_32x8: return {32, 8, 128};
-    default: return {32, 16, 256};
+    case TILE_16x32: return {16, 32, 512};
+    case TILE_64x8: return {64, 8, 512};
+    case TILE_32x8: return {32, 8, 256};
+    default: return {32, 16, 512};
     }
 }
 

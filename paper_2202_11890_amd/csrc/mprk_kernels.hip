@@ -788,6 +788,16 @@ using S1 = Shape<16, 32>;
 using S2 = Shape<64, 8>;
 using S3 = Shape<32, 8>;
 
+// The host's view of each shape (tile counts) must match the kernels'.
+template <class S>
+constexpr bool same_dims(int shape)
+{
+    return tile_dims(shape).tx == S::TX && tile_dims(shape).tz == S::TZ && tile_dims(shape).nt == S::NT;
+}
+static_assert(same_dims<S0>(TILE_32x16) && same_dims<S1>(TILE_16x32) && same_dims<S2>(TILE_64x8) &&
+                  same_dims<S3>(TILE_32x8),
+              "tile shape table");
+
 // Calls f.template operator()<FT, S>() for the flux type and shape.
 template <class F>
 auto with_kernel(bool flux32, int shape, F&& f)
