@@ -40,7 +40,7 @@ struct Shape {
     static constexpr int LOAD_THREADS = LOAD_RG * HX;
     static constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG;  // rows per loader thread
     static_assert(Z % C == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
-    static_assert(NT >= 64 + X && Z <= 64, "edge faces use waves 0 and 1");
+    static_assert(NT >= X + Z, "one edge face per thread of the first X + Z");
     static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
     static_assert(LOAD_RG >= 1, "loader needs a full row of threads");
     // Shared memory of one tile: the staged state and primitives in the flux
@@ -113,16 +113,18 @@ __device__ __forceinline__ int pidx(int f, int r, int c) { return (f * S::PZ + r
 enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
 
 // Numerical flux (inviscid minus viscous) through the face between tile cell
-// (c, r) and its +dir neighbour, in the face-normal frame: returns
+// (c, r) and its +dir neighbour (dir 0: x, 1: z; a constant at the interior
+// call sites, a per-lane value for the edge faces), in the face-normal frame:
+// returns
 // (F_rho, F_normal-momentum, F_tangential-momentum, F_energy), in FT.
 //   kind FACE_TOP:    (c, r) is the top interior row; the other side is its
 //                     mirror (wall or interface).
 //   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; likewise.
 // At walls and at the interface the viscous part is not added here: walls
 // carry none, and the interface flux enters the divergence in FP64.
-template <class FT, int dir, class S>
+template <class FT, class S>
 __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& D, const Lds<FT>& L,
-                                          int c, int r, int kind, FT F[NV])
+                                          int dir, int c, int r, int kind, FT F[NV])
 {
     // A face on a tile edge is computed by the tiles on both sides, at
     // different call sites.  With contraction off and the fused operations
@@ -132,11 +134,11 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     MPRK_SHAPE_CONSTANTS(S);
     const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
     const FT h = FT(0.5), q4 = FT(0.25);
-    constexpr int sn = dir ? HX : 1;         // normal stride in the state tile
-    constexpr int vn = dir ? 2 : 1;          // normal momentum component
-    constexpr int vt = dir ? 1 : 2;          // tangential momentum component
+    const int sn = dir ? HX : 1;             // normal stride in the state tile
+    const int vn = dir ? 2 : 1;              // normal momentum component
+    const int vt = dir ? 1 : 2;              // tangential momentum component
     constexpr int plane = HZ * HX;
-    constexpr int comp[NV] = {0, vn, vt, 3};
+    const int comp[NV] = {0, vn, vt, 3};
 
     // Reconstruction of conserved variables with central cell gradients:
     // qL = q_c + (q_{c+1} - q_{c-1})/4, qR = q_{c+1} - (q_{c+2} - q_c)/4.
@@ -196,10 +198,10 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
         // Common values: averaged velocity, normal derivative by finite
         // difference, tangential derivative by averaging cell gradients.
         const int pb = pidx<S>(0, r, c);
-        constexpr int pn = dir ? PX : 1;
-        constexpr int pt = dir ? 1 : PX;
-        constexpr int fn = dir ? 1 : 0;      // normal velocity in the primitive tile
-        constexpr int ft = dir ? 0 : 1;
+        const int pn = dir ? PX : 1;
+        const int pt = dir ? 1 : PX;
+        const int fn = dir ? 1 : 0;          // normal velocity in the primitive tile
+        const int ft = dir ? 0 : 1;
         constexpr int pp = PZ * PX;
         const FT* Un = L.p + fn * pp + pb;
         const FT* Ut = L.p + ft * pp + pb;
@@ -343,28 +345,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     __syncthreads();
 
     // ---- faces: the x-face right of each of the thread's cells, the z-face
-    // above it, and one edge face: the x-face left of column 0 on each
-    // computed row (wave 0) or the z-face below the first computed row
-    // (wave 1), so that no wave runs both directions.
-    const bool ex_x4 = tid < TZ && tid >= vs && tid < ve;
-    const int ez = tid - 64;
-    const bool ex_z4 = ez >= 0 && ez < TX && ez < ncols;
+    // above it, and one edge face per thread of the first TZ + TX: the
+    // x-face left of column 0 on row e (e < TZ) or the z-face below the first
+    // computed row in column e - TZ.  The edge faces of both directions share
+    // one pass of the face code (the direction is a per-lane value), which
+    // only the first wave(s) run.
     const int re = vs - 1;
-    const int kind4 = (z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
+    const bool e_z = tid >= TZ;
+    const int e_c = e_z ? tid - TZ : -1;
+    const int e_r = e_z ? re : tid;
+    const bool ex_e = e_z ? (tid - TZ < TX && tid - TZ < ncols) : (tid >= vs && tid < ve);
+    const int kind_e = (e_z && z0 + vs == 0) ? FACE_BOTTOM : FACE_INTERIOR;
 
     // F[h]: x-face right of cell h; F[CZ + h]: z-face above it; F[2 CZ]: edge face.
     FT F[2 * CZ + 1][NV];
 #pragma unroll
     for (int h = 0; h < CZ; ++h)
-        if (okc[h]) face_flux<FT, 0, S>(A, D, L, c, r0 + h, FACE_INTERIOR, F[h]);
+        if (okc[h]) face_flux<FT, S>(A, D, L, 0, c, r0 + h, FACE_INTERIOR, F[h]);
 #pragma unroll
     for (int h = 0; h < CZ; ++h)
         if (okc[h]) {
             const int kind = (z0 + r0 + h == nz - 1) ? FACE_TOP : FACE_INTERIOR;
-            face_flux<FT, 1, S>(A, D, L, c, r0 + h, kind, F[CZ + h]);
+            face_flux<FT, S>(A, D, L, 1, c, r0 + h, kind, F[CZ + h]);
         }
-    if (ex_x4) face_flux<FT, 0, S>(A, D, L, -1, tid, FACE_INTERIOR, F[2 * CZ]);
-    if (ex_z4) face_flux<FT, 1, S>(A, D, L, ez, re, kind4, F[2 * CZ]);
+    if (ex_e) face_flux<FT, S>(A, D, L, e_z ? 1 : 0, e_c, e_r, kind_e, F[2 * CZ]);
 
     __builtin_amdgcn_s_setprio(2);
     // Pointwise FP64 reads for the combination (the stage value itself when
@@ -415,8 +419,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
 #pragma unroll
     for (int h = 0; h < CZ; ++h)
         if (okc[h]) { put_x(c, r0 + h, F[h]); put_z(c, r0 + h, F[CZ + h]); }
-    if (ex_x4) put_x(-1, tid, F[2 * CZ]);
-    if (ex_z4) put_z(ez, re, F[2 * CZ]);
+    if (ex_e) {
+        if (e_z) put_z(e_c, re, F[2 * CZ]);
+        else put_x(-1, tid, F[2 * CZ]);
+    }
     __syncthreads();
 
     // ---- divergence (FP64: differences of two face fluxes are exact for FP32
