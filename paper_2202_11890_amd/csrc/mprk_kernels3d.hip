@@ -395,8 +395,11 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
         face3<FT, 1, S>(A, D, L, cx, cy, r0 + hh, F3_INTERIOR, F[3 * hh + 1]);
         face3<FT, 2, S>(A, D, L, cx, cy, r0 + hh, kz, F[3 * hh + 2]);
     }
-    // Edge faces: ne_x = TY*TZ (x = -1), ne_y = TX*TZ (y = -1), ne_z = TX*TY (below vs).
-    constexpr int NEX = TY * TZ, NEY = TX * TZ, NEZ = TX * TY, NE = NEX + NEY + NEZ;
+    // Edge faces: ne_x = TY*TZ (x = -1), ne_y = TX*TZ (y = -1), ne_z = TX*TY
+    // (below vs).  Each direction's range of edge indices starts at a wave
+    // boundary, so that no wave runs the face code of two directions.
+    constexpr int NEX = TY * TZ, NEY = TX * TZ, NEZ = TX * TY;
+    constexpr int OEY = (NEX + 63) / 64 * 64, OEZ = OEY + (NEY + 63) / 64 * 64, NE = OEZ + NEZ;
     constexpr int EPT = (NE + NT - 1) / NT;
     FT E[EPT][NV3];
     int ekind[EPT];
@@ -410,14 +413,14 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
                 face3<FT, 0, S>(A, D, L, -1, yy, zz, F3_INTERIOR, E[u]);
                 ekind[u] = 0;
             }
-        } else if (e < NEX + NEY) {
-            const int f = e - NEX, xx = f % TX, zz = f / TX;
+        } else if (e >= OEY && e < OEY + NEY) {
+            const int f = e - OEY, xx = f % TX, zz = f / TX;
             if (xx < ncx && zz >= vs && zz < ve) {
                 face3<FT, 1, S>(A, D, L, xx, -1, zz, F3_INTERIOR, E[u]);
                 ekind[u] = 1;
             }
-        } else if (e < NE) {
-            const int f = e - NEX - NEY, xx = f % TX, yy = f / TX;
+        } else if (e >= OEZ && e < NE) {
+            const int f = e - OEZ, xx = f % TX, yy = f / TX;
             if (xx < ncx && yy < ncy) {
                 const int kind = (z0 + vs == 0) ? F3_BOTTOM : F3_INTERIOR;
                 face3<FT, 2, S>(A, D, L, xx, yy, vs - 1, kind, E[u]);
@@ -477,8 +480,8 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     for (int u = 0; u < EPT; ++u) {
         const int e = tid + u * NT;
         if (ekind[u] == 0) put(0, -1, e % TY, e / TY, E[u]);
-        else if (ekind[u] == 1) { const int f = e - NEX; put(1, f % TX, -1, f / TX, E[u]); }
-        else if (ekind[u] == 2) { const int f = e - NEX - NEY; put(2, f % TX, f / TX, vs - 1, E[u]); }
+        else if (ekind[u] == 1) { const int f = e - OEY; put(1, f % TX, -1, f / TX, E[u]); }
+        else if (ekind[u] == 2) { const int f = e - OEZ; put(2, f % TX, f / TX, vs - 1, E[u]); }
     }
     __syncthreads();
 
