@@ -192,13 +192,15 @@ def test_run_matches_oracle(name, w, n):
     assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
 
 
-def test_large_five_steps_matches_oracle():
+def test_large_fifty_steps_matches_oracle():
+    """The 1024 x 512 workload, 50 slow steps (the oracle takes 10-30 s)."""
     w = inputs.large()
-    say("run large 5 steps")
+    say("run large 50 steps")
     ql, qu = inputs.initial_state(w)
     dt = oracle.dt_rule(problem_of(w), ql, qu, w.m)
-    (gl, gu), st = run_gpu(w, ql, qu, dt, 5)
-    ol, ou = run_oracle(w, ql, qu, dt, 5)
+    (gl, gu), st = run_gpu(w, ql, qu, dt, 50)
+    assert st["status"] == 0 and st["steps_done"] == 50
+    ol, ou = run_oracle(w, ql, qu, dt, 50)
     el, eu = state_err(gl, ol), state_err(gu, ou)
     say("  err lower", el, "upper", eu)
     assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
