@@ -79,9 +79,13 @@ KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h", "mprk_
 
 
 def kernel_source_hash(kernel: str = "stage_kernel"):
+    """Hash of a kernel's sources and of their per-source compiler flags."""
+    from __graft_entry__ import EXTRA_FLAGS
+
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_2202_11890_amd", "csrc", f), "rb").read())
+        h.update(" ".join(EXTRA_FLAGS.get(f, [])).encode())
     return h.hexdigest()[:16]
 
 
