@@ -13,6 +13,8 @@ Tolerances (derived from the arithmetic):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 
@@ -201,6 +203,27 @@ def test_large_fifty_steps_matches_oracle():
     (gl, gu), st = run_gpu(w, ql, qu, dt, 50)
     assert st["status"] == 0 and st["steps_done"] == 50
     ol, ou = run_oracle(w, ql, qu, dt, 50)
+    el, eu = state_err(gl, ol), state_err(gu, ou)
+    say("  err lower", el, "upper", eu)
+    assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
+
+
+@pytest.mark.skipif(not os.environ.get("MPRK_LONG_PARITY"),
+                    reason="about five minutes of oracle time; set MPRK_LONG_PARITY=1 to run")
+def test_large_thousand_steps_matches_oracle():
+    """The whole 1024 x 512 benchmark run (1000 slow steps) against the oracle,
+    which runs in chunks of 50 steps (restarts are bitwise) and reports its
+    progress."""
+    w = inputs.large()
+    ql, qu = inputs.initial_state(w)
+    dt = oracle.dt_rule(problem_of(w), ql, qu, w.m)
+    (gl, gu), st = run_gpu(w, ql, qu, dt, w.steps)
+    assert st["status"] == 0 and st["steps_done"] == w.steps
+    ol, ou = ql.copy(), qu.copy()
+    pb = problem_of(w)
+    for done in range(0, w.steps, 50):
+        oracle.mprk_run(pb, w.base, w.m, dt, min(50, w.steps - done), ol, ou)
+        say("  oracle", done + 50, "steps")
     el, eu = state_err(gl, ol), state_err(gu, ou)
     say("  err lower", el, "upper", eu)
     assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
