@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -78,13 +79,22 @@ KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h", "mprk_
                   "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h", "mprk_device.h")}
 
 
+def code_text(path: str) -> bytes:
+    """A source file without its comments and blank lines (the sources hold
+    no string literal containing a comment marker)."""
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln).encode()
+
+
 def kernel_source_hash(kernel: str = "stage_kernel"):
-    """Hash of a kernel's sources and of their per-source compiler flags."""
+    """Hash of a kernel's code (comments aside) and of its per-source compiler
+    flags."""
     from __graft_entry__ import EXTRA_FLAGS
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
-        h.update(open(os.path.join(ROOT, "paper_2202_11890_amd", "csrc", f), "rb").read())
+        h.update(code_text(os.path.join(ROOT, "paper_2202_11890_amd", "csrc", f)))
         h.update(" ".join(EXTRA_FLAGS.get(f, [])).encode())
     return h.hexdigest()[:16]
 

@@ -15,7 +15,7 @@
 // edge faces) by a single direction-generic face routine; the fluxes are
 // exchanged through LDS (aliasing the staged state) and each thread forms the
 // divergence of its cells.  One cell per thread keeps the register count low
-// (74 VGPRs in FP64, 48 in FP32), so more waves hide the LDS and HBM latency
+// (76 VGPRs in FP64, 48 in FP32), so more waves hide the LDS and HBM latency
 // than with two cells per thread.
 //
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
