@@ -549,7 +549,7 @@ struct mprk_batch {
     std::vector<int> rec0;                    // first stage record of each member
     std::vector<int> slot_stage;              // [member][slot]: stage record or -1
     // device tables (offsets into ws)
-    size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    size_t off_tab, off_proxy, off_bmap, off_slots, off_ptiles, off_pmember, off_pdone;
     size_t off_red, off_finals;
     bool red_ready = false;
     std::vector<ReduceArgs> h_red;
@@ -559,7 +559,7 @@ struct mprk_batch {
     bool rec_dirty = false;                   // steps changed: stage records to rewrite
     int rec_dev = 0;                          // dev_stores of the records on the device
     std::vector<StageArgs> h_tab, h_proxy;
-    std::vector<BatchEntry> h_ent;            // [slot][member] (first count entries used)
+    std::vector<BatchEntry> h_bmap;           // [slot][block] (first slot_blocks entries used)
     std::vector<int> slot_count, slot_blocks;
     std::vector<TileRef> h_tiles;
     std::vector<MemberRun> h_mr;
@@ -570,7 +570,7 @@ struct mprk_batch {
     StepGraph graph;
     int graph_shape = -1;
     std::vector<std::vector<void*>> g_args;   // per node: pointers to its argument values
-    struct NodeArgs { const StageArgs* tab; const BatchEntry* ent; int nent; int nblocks; };
+    struct NodeArgs { const StageArgs* tab; const BatchEntry* bmap; int nblocks; };
     std::vector<NodeArgs> g_vals;
     std::vector<double> host_final;           // [member][2*RED_FIELDS]
     double adapt_cr = 0.0, adapt_dn = 0.0;    // adaptive steps at check points (cr 0: off)
@@ -765,7 +765,7 @@ int run_reduce(mprk_ctx* c, mprk_stats* out)
 
 struct BatchLayout {
     std::vector<size_t> core_off;
-    size_t off_tab, off_proxy, off_ent, off_slots, off_ptiles, off_pmember, off_pdone;
+    size_t off_tab, off_proxy, off_bmap, off_slots, off_ptiles, off_pmember, off_pdone;
     size_t off_red, off_finals;
     int nslots, total_ms, max_tiles;
     size_t total;
@@ -822,8 +822,8 @@ bool batch_layout(const mprk_member* mem, int32_t n, BatchLayout* L)
     off += round_up((size_t)total_ms * sizeof(StageArgs));
     L->off_proxy = off;
     off += round_up((size_t)total_ms * sizeof(StageArgs));
-    L->off_ent = off;
-    off += round_up((size_t)ms_max * n * sizeof(BatchEntry));
+    L->off_bmap = off;   // per slot, one entry per block (at most every member's largest tile count)
+    off += round_up((size_t)ms_max * tiles * sizeof(BatchEntry));
     L->off_slots = off;
     off += round_up((size_t)ms_max * n * sizeof(int32_t));
     L->off_ptiles = off;
@@ -884,7 +884,8 @@ int batch_tables(mprk_batch* b)
     const int n = b->n, L = b->nslots;
     b->h_tab.clear();
     b->h_proxy.clear();
-    b->h_ent.assign((size_t)L * n, BatchEntry{0, 0});
+    const size_t T = (size_t)b->max_tiles;
+    b->h_bmap.assign((size_t)L * T, BatchEntry{0, 0});
     b->slot_count.assign(L, 0);
     b->slot_blocks.assign(L, 0);
     b->h_slots.assign((size_t)n * L, -1);
@@ -906,7 +907,9 @@ int batch_tables(mprk_batch* b)
         for (int i = 0; i < n; ++i) {
             const int r = b->h_slots[(size_t)i * L + l];
             if (r < 0 || b->h_tab[r].nblocks <= 0) continue;
-            b->h_ent[(size_t)l * n + cnt] = BatchEntry{r, blocks};
+            if ((size_t)blocks + (size_t)b->h_tab[r].nblocks > T) return MPRK_EINVAL;   // cannot happen
+            for (int t = 0; t < b->h_tab[r].nblocks; ++t)
+                b->h_bmap[(size_t)l * T + blocks + t] = BatchEntry{r, blocks};
             blocks += b->h_tab[r].nblocks;
             ++cnt;
         }
@@ -935,7 +938,7 @@ int batch_tables(mprk_batch* b)
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(b->ws + b->off_proxy, b->h_proxy.data(), b->h_proxy.size() * sizeof(StageArgs),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(b->ws + b->off_ent, b->h_ent.data(), b->h_ent.size() * sizeof(BatchEntry),
+        hipMemcpyAsync(b->ws + b->off_bmap, b->h_bmap.data(), b->h_bmap.size() * sizeof(BatchEntry),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(b->ws + b->off_slots, b->h_slots.data(), b->h_slots.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -953,10 +956,10 @@ int batch_tables(mprk_batch* b)
 int batch_step_launches(mprk_batch* b, bool proxy)
 {
     const StageArgs* tab = (const StageArgs*)(b->ws + (proxy ? b->off_proxy : b->off_tab));
-    const BatchEntry* ent = (const BatchEntry*)(b->ws + b->off_ent);
+    const BatchEntry* bmap = (const BatchEntry*)(b->ws + b->off_bmap);
     for (int l = 0; l < b->nslots; ++l) {
         if (b->slot_count[l] == 0) continue;
-        if (launch_batch(tab, ent + (size_t)l * b->n, b->slot_count[l], b->slot_blocks[l], b->flux32, b->shape,
+        if (launch_batch(tab, bmap + (size_t)l * b->max_tiles, b->slot_blocks[l], b->flux32, b->shape,
                          b->stream) != hipSuccess)
             return MPRK_EHIP;
     }
@@ -968,7 +971,7 @@ int batch_graph(mprk_batch* b)
     if (b->graph.exec && b->graph_shape == b->shape) return MPRK_OK;
     const int L = b->nslots;
     b->g_vals.assign(L, mprk_batch::NodeArgs{});
-    b->g_args.assign(L, std::vector<void*>(4, nullptr));
+    b->g_args.assign(L, std::vector<void*>(3, nullptr));
     if (!b->graph.begin()) return MPRK_EHIP;
     const KernelRef kr = batch_kernel_ref(b->flux32, b->shape);
     hipGraphNode_t prev = nullptr;
@@ -976,14 +979,12 @@ int batch_graph(mprk_batch* b)
         if (b->slot_count[l] == 0) continue;
         mprk_batch::NodeArgs& v = b->g_vals[l];
         v.tab = (const StageArgs*)(b->ws + b->off_tab);
-        v.ent = (const BatchEntry*)(b->ws + b->off_ent) + (size_t)l * b->n;
-        v.nent = b->slot_count[l];
+        v.bmap = (const BatchEntry*)(b->ws + b->off_bmap) + (size_t)l * b->max_tiles;
         v.nblocks = b->slot_blocks[l];
         std::vector<void*>& a = b->g_args[l];
         a[0] = &v.tab;
-        a[1] = &v.ent;
-        a[2] = &v.nent;
-        a[3] = &v.nblocks;
+        a[1] = &v.bmap;
+        a[2] = &v.nblocks;
         if (!b->graph.add(kr, v.nblocks, a.data(), &prev)) {
             b->graph.reset();
             return MPRK_EHIP;
@@ -1424,7 +1425,7 @@ int mprk_batch_create(const mprk_member* members, int32_t n, void* workspace, si
     b->max_tiles = L.max_tiles;
     b->off_tab = L.off_tab;
     b->off_proxy = L.off_proxy;
-    b->off_ent = L.off_ent;
+    b->off_bmap = L.off_bmap;
     b->off_slots = L.off_slots;
     b->off_ptiles = L.off_ptiles;
     b->off_pmember = L.off_pmember;

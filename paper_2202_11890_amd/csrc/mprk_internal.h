@@ -154,11 +154,12 @@ struct PersistArgs {
 };
 
 // Batched launches: the blocks of one launch are split into consecutive
-// ranges, one per entry; an entry names the stage record (of some member)
-// whose tiles its blocks compute.
+// ranges, one per member with a stage in the launch; each block finds its
+// range in a per-block map whose entry names the stage record (of some
+// member) that its range computes.
 struct BatchEntry {
     int32_t arg;       // index into the stage-record table
-    int32_t begin;     // first block of this entry
+    int32_t begin;     // first block of this block's range
 };
 
 // Kernel of a launch, for building graphs: function, block size and the
@@ -170,7 +171,7 @@ struct KernelRef {
 
 hipError_t launch_stage(const StageArgs& a, int shape, hipStream_t s);
 KernelRef stage_kernel_ref(bool flux32, int shape);
-hipError_t launch_batch(const StageArgs* tab, const BatchEntry* ent, int nent, int nblocks, bool flux32,
+hipError_t launch_batch(const StageArgs* tab, const BatchEntry* bmap, int nblocks, bool flux32,
                         int shape, hipStream_t s);
 KernelRef batch_kernel_ref(bool flux32, int shape);
 hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int shape, hipStream_t s);

@@ -528,22 +528,17 @@ void stage_kernel(const StageArgs A)
 }
 
 // One launch over several stage records (batched members): blocks are
-// remapped so that each XCD takes a contiguous range, then located in the
-// entry table (a uniform binary search over the entries' first blocks).
+// remapped so that each XCD takes a contiguous range, then look up their
+// range's stage record in the per-block map (one uniform load; a binary
+// search over the ranges took a chain of dependent loads per workgroup).
 template <class FT, class S>
 __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(MPRK_WAVES_PER_EU)))
-void batch_kernel(const StageArgs* __restrict__ tab, const BatchEntry* __restrict__ ent, int nent,
-                  int nblocks)
+void batch_kernel(const StageArgs* __restrict__ tab, const BatchEntry* __restrict__ bmap, int nblocks)
 {
     __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
     const int b = xcd_contiguous(blockIdx.x, nblocks);
-    int lo = 0, hi = nent - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ent[mid].begin <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    record_block<FT, S>(tab[ent[lo].arg], b - ent[lo].begin, false, smem);
+    const BatchEntry e = bmap[b];
+    record_block<FT, S>(tab[e.arg], b - e.begin, false, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,12 +829,12 @@ KernelRef stage_kernel_ref(bool flux32, int shape)
     });
 }
 
-hipError_t launch_batch(const StageArgs* tab, const BatchEntry* ent, int nent, int nblocks, bool flux32,
-                        int shape, hipStream_t s)
+hipError_t launch_batch(const StageArgs* tab, const BatchEntry* bmap, int nblocks, bool flux32, int shape,
+                        hipStream_t s)
 {
-    if (nblocks <= 0 || nent <= 0) return hipSuccess;
+    if (nblocks <= 0) return hipSuccess;
     return with_kernel(flux32, shape, [&]<class FT, class S>() {
-        hipLaunchKernelGGL((batch_kernel<FT, S>), dim3(nblocks), dim3(S::NT), 0, s, tab, ent, nent, nblocks);
+        hipLaunchKernelGGL((batch_kernel<FT, S>), dim3(nblocks), dim3(S::NT), 0, s, tab, bmap, nblocks);
         return hipGetLastError();
     });
 }
