@@ -250,3 +250,13 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_committed_counter_profiles_match_the_kernels():
+    """The HBM-traffic summaries under profiles/ were taken with the current
+    stage kernels (their hash covers the kernels' code without comments and
+    the per-source compiler flags), so the benchmark reports their traffic."""
+    import bench
+
+    for kernel, workload in (("stage_kernel", "large"), ("stage_kernel3", "large3d")):
+        assert bench.traffic_from_profiles(workload, kernel) is not None, (kernel, workload)
