@@ -57,14 +57,18 @@ struct Shape {
     (void)TX; (void)TZ; (void)NT; (void)HX; (void)HZ; (void)PX; (void)PZ
 
 // Cell primitives u, w, T in the flux type (staged for the viscous fluxes).
+// A cell's primitives are computed by every tile that stages it; contraction
+// is off and the fused operations are written out, so every tile obtains the
+// same bits (the face fluxes built from them must agree across tiles).
 template <class FT>
 __device__ __forceinline__ void primitives(FT rho, FT mx, FT mz, FT en, FT gamma, FT gm1, FT& u,
                                            FT& w, FT& T)
 {
+#pragma clang fp contract(off)
     const FT ir = Fm<FT>::rcp(rho);
     u = mx * ir;
     w = mz * ir;
-    const FT p = gm1 * (en - FT(0.5) * (mx * u + mz * w));
+    const FT p = gm1 * fma(FT(-0.5), fma(mx, u, mz * w), en);
     T = gamma * p * ir;
 }
 
@@ -302,9 +306,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         for (int k = 0; k < LOAD_ROWS; ++k) {
             const int zr = rg + LOAD_RG * k;
             if (zr < HZ) {
+                FT q[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    L.q[(v * HZ + zr) * HX + xc] = FT((v == 2 && neg[k]) ? -val[k][v] : val[k][v]);
+                for (int v = 0; v < NV; ++v) {
+                    q[v] = FT((v == 2 && neg[k]) ? -val[k][v] : val[k][v]);
+                    L.q[(v * HZ + zr) * HX + xc] = q[v];
+                }
+                // Primitives of the tile and its 1-cell ring, from the same
+                // staged values (primitive cell (zr - 1, xc - 1)).
+                if (xc >= 1 && xc <= HX - 2 && zr >= 1 && zr <= HZ - 2) {
+                    FT u, w, T;
+                    primitives<FT>(q[0], q[1], q[2], q[3], FT(A.gamma), FT(A.gm1), u, w, T);
+                    const int pi = (zr - 1) * PX + xc - 1;
+                    L.p[pi] = u;
+                    L.p[PZ * PX + pi] = w;
+                    L.p[2 * PZ * PX + pi] = T;
+                }
             }
         }
     }
@@ -330,19 +347,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     __syncthreads();
 
     __builtin_amdgcn_s_setprio(0);
-
-    // ---- primitives on the tile plus a 1-cell ring
-    for (int idx = tid; idx < PZ * PX; idx += NT) {
-        const int pr = idx / PX, pc = idx - pr * PX;
-        const int b = qidx<S>(0, pr - 1, pc - 1);
-        FT u, w, T;
-        primitives<FT>(L.q[b], L.q[b + HZ * HX], L.q[b + 2 * HZ * HX], L.q[b + 3 * HZ * HX],
-                       FT(A.gamma), FT(A.gm1), u, w, T);
-        L.p[idx] = u;
-        L.p[PZ * PX + idx] = w;
-        L.p[2 * PZ * PX + idx] = T;
-    }
-    __syncthreads();
 
     // ---- faces: the x-face right of each of the thread's cells, the z-face
     // above it, and one edge face per thread of the first TZ + TX: the

@@ -79,11 +79,14 @@ enum : int { F3_INTERIOR = 0, F3_TOP = 1, F3_BOTTOM = 2 };
 template <class FT>
 __device__ __forceinline__ void prim3(const FT* c, FT gamma, FT gm1, FT& u, FT& v, FT& w, FT& T)
 {
+    // Every tile that stages a cell computes its primitives: contraction off
+    // and the fused operations written out, so all obtain the same bits.
+#pragma clang fp contract(off)
     const FT ir = Fm<FT>::rcp(c[0]);
     u = c[1] * ir;
     v = c[2] * ir;
     w = c[3] * ir;
-    const FT p = gm1 * (c[4] - FT(0.5) * (c[1] * u + c[2] * v + c[3] * w));
+    const FT p = gm1 * fma(FT(-0.5), fma(c[1], u, fma(c[2], v, c[3] * w)), c[4]);
     T = gamma * p * ir;
 }
 
@@ -301,6 +304,7 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     // fluxes, 1% with FP32); the global loads of LOAD_B planes are issued
     // before any is stored.
     constexpr int NCELL = HZ * HY * HX;
+    constexpr int NPC = PZ * PY * PX;
     constexpr int PXY = HY * HX;
     constexpr int LOAD_RG = NT / PXY;
     static_assert(LOAD_RG >= 1, "loader needs a full plane of threads");
@@ -347,9 +351,23 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
                 const int zz = rg + LOAD_RG * (k0 + u);
                 if (k0 + u < LOAD_PL && zz < HZ) {
                     const int idx = zz * PXY + pos;
+                    FT c[NV3];
 #pragma unroll
-                    for (int v = 0; v < NV3; ++v)
-                        L.q[v * NCELL + idx] = FT((v == 3 && neg[u]) ? -val[u][v] : val[u][v]);
+                    for (int v = 0; v < NV3; ++v) {
+                        c[v] = FT((v == 3 && neg[u]) ? -val[u][v] : val[u][v]);
+                        L.q[v * NCELL + idx] = c[v];
+                    }
+                    // Primitives of the tile and its 1-cell ring, from the
+                    // same staged values (primitive cell (zz-1, yy-1, xx-1)).
+                    if (xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= HY - 2 && zz >= 1 && zz <= HZ - 2) {
+                        FT pu, pv, pw, pT;
+                        prim3<FT>(c, FT(A.gamma), FT(A.gm1), pu, pv, pw, pT);
+                        const int pi = ((zz - 1) * PY + yy - 1) * PX + xx - 1;
+                        L.p[pi] = pu;
+                        L.p[NPC + pi] = pv;
+                        L.p[2 * NPC + pi] = pw;
+                        L.p[3 * NPC + pi] = pT;
+                    }
                 }
             }
         }
@@ -382,23 +400,6 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
     __syncthreads();
 
     __builtin_amdgcn_s_setprio(0);
-    // ---- primitives on the tile plus a 1-cell ring
-    constexpr int NPC = PZ * PY * PX;
-    for (int idx = tid; idx < NPC; idx += NT) {
-        const int zz = idx / (PY * PX), rem = idx - zz * (PY * PX);
-        const int yy = rem / PX, xx = rem - yy * PX;
-        const int b = q3<S>(0, zz - 1, yy - 1, xx - 1);
-        FT c[NV3];
-#pragma unroll
-        for (int v = 0; v < NV3; ++v) c[v] = L.q[v * NCELL + b];
-        FT u, v, w, T;
-        prim3<FT>(c, FT(A.gamma), FT(A.gm1), u, v, w, T);
-        L.p[idx] = u;
-        L.p[NPC + idx] = v;
-        L.p[2 * NPC + idx] = w;
-        L.p[3 * NPC + idx] = T;
-    }
-    __syncthreads();
 
     // ---- faces: x+, y+, z+ of the thread's cells, then the edge faces
     // (x left of column 0, y in front of row 0, z below the first computed
