@@ -439,12 +439,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         const int r = r0 + h;
         const int row = z0 + r;
         double R[NV];
+        // The right x-face and the top z-face are this thread's own (still in
+        // registers; the z-face in its normal frame); the left and bottom
+        // ones come from the exchange.
+        constexpr int zmap[NV] = {0, 2, 1, 3};
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const FT* fx = ex_x + v * TZ * (TX + 1) + r * (TX + 1) + c;
             const FT* fz = ex_z + v * (TZ + 1) * TX + r * TX + c;
-            R[v] = -((double)fx[1] - (double)fx[0]) * A.inv_dx -
-                   ((double)fz[TX] - (double)fz[0]) * D.inv_dz;
+            R[v] = -((double)F[h][v] - (double)fx[0]) * A.inv_dx -
+                   ((double)F[CZ + h][zmap[v]] - (double)fz[0]) * D.inv_dz;
         }
         // Interface viscous flux (FP64, same bits on both sides): it leaves the
         // lower domain through its top face and enters the upper domain

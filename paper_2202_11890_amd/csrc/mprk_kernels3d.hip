@@ -516,8 +516,11 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
             const FT* fx = ex_x + v * S::EXX + (zz * TY + cy) * (TX + 1) + cx;
             const FT* fy = ex_y + v * S::EXY + (zz * (TY + 1) + cy) * TX + cx;
             const FT* fz = ex_z + v * S::EXZ + (zz * TY + cy) * TX + cx;
-            R[v] = -((double)fx[1] - (double)fx[0]) * inv_dx - ((double)fy[TX] - (double)fy[0]) * inv_dy -
-                   ((double)fz[TY * TX] - (double)fz[0]) * inv_dz;
+            // The +x, +y and +z faces are this thread's own (still in
+            // registers); the other three come from the exchange.
+            R[v] = -((double)F[3 * hh][v] - (double)fx[0]) * inv_dx -
+                   ((double)F[3 * hh + 1][v] - (double)fy[0]) * inv_dy -
+                   ((double)F[3 * hh + 2][v] - (double)fz[0]) * inv_dz;
         }
         const int gc = cy * TX + cx;
         if (DOM == 0 && D.gamma_top && row == nz - 1) {
