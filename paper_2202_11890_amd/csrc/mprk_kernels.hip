@@ -9,14 +9,17 @@
 //
 // Tiling: a workgroup of 512 threads owns a 32 x 16 tile of one domain, one
 // cell per thread (other tile shapes and cells-per-thread counts are template
-// parameters).  The tile's conserved state (2-cell halo) and primitives u, w,
-// T (1-cell halo) are staged in LDS; every face of the tile is computed
-// exactly once (two faces per cell plus one left column and one bottom row of
-// edge faces) by a single direction-generic face routine; the fluxes are
-// exchanged through LDS (aliasing the staged state) and each thread forms the
-// divergence of its cells.  One cell per thread keeps the register count low
-// (76 VGPRs in FP64, 48 in FP32), so more waves hide the LDS and HBM latency
-// than with two cells per thread.
+// parameters).  The tile's conserved state (2-cell halo) is staged in LDS,
+// and the loader threads compute the primitives u, w, T of the tile and its
+// 1-cell ring from the values they stage (no separate pass); every face of
+// the tile is computed exactly once (two faces per cell plus one left column
+// and one bottom row of edge faces) by a single direction-generic face
+// routine; the fluxes are exchanged through LDS (aliasing the staged state)
+// and each thread forms the divergence of its cells from its own two face
+// fluxes (registers) and its neighbours' two (LDS).  Three barriers per
+// tile.  One cell per thread keeps the register count low (76 VGPRs in FP64,
+// 48 in FP32), so more waves hide the LDS and HBM latency than with two
+// cells per thread.
 //
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
 // stability measures and the physical-state flag.
