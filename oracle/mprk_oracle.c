@@ -69,6 +69,12 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 /* Indexing: q[v][k][i], x fastest, k = 0 is the bottom row.                */
 /* ------------------------------------------------------------------------ */
+/* Loops over fewer cells than this run on one thread: thread start-up would
+ * cost more than the loop (results do not depend on the thread count, every
+ * output element being written by exactly one iteration). */
+#define ORC_PAR_MIN_CELLS 16384
+static inline int par_ok(size_t cells) { return cells >= ORC_PAR_MIN_CELLS; }
+
 static inline size_t at(int nx, int nz, int v, int k, int i)
 {
     return ((size_t)v * (size_t)nz + (size_t)k) * (size_t)nx + (size_t)i;
@@ -221,7 +227,7 @@ static void domain_rhs(const dom_t* D, const double* q, const double* fvg,
     double* Fx = (double*)malloc(sizeof(double) * NV * (size_t)nz * nx);
     double* Fz = (double*)malloc(sizeof(double) * NV * (size_t)(nz + 1) * nx);
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * nz))
     for (int e = 0; e < ne; ++e) {
         int k = e - 1;
         int src = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
@@ -238,7 +244,7 @@ static void domain_rhs(const dom_t* D, const double* q, const double* fvg,
         }
     }
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * nz))
     for (int k = 0; k < nz; ++k) {
         int e = k + 1;
         for (int i = 0; i < nx; ++i) {
@@ -258,7 +264,7 @@ static void domain_rhs(const dom_t* D, const double* q, const double* fvg,
     }
 
     /* x-faces on the requested rows. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * nz))
     for (int k = k_lo; k < k_hi; ++k) {
         int e = k + 1;
         for (int i = 0; i < nx; ++i) {
@@ -287,7 +293,7 @@ static void domain_rhs(const dom_t* D, const double* q, const double* fvg,
     }
 
     /* z-faces f = k_lo .. k_hi (below row f). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * nz))
     for (int f = k_lo; f <= k_hi; ++f) {
         for (int i = 0; i < nx; ++i) {
             double qL[NV], qR[NV], F[NV], fv[NV] = {0.0, 0.0, 0.0, 0.0};
@@ -330,7 +336,7 @@ static void domain_rhs(const dom_t* D, const double* q, const double* fvg,
     }
 
     /* Divergence plus source. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * nz))
     for (int k = k_lo; k < k_hi; ++k) {
         for (int i = 0; i < nx; ++i) {
             int im = wrap(i - 1, nx);
@@ -582,7 +588,7 @@ int orc_mprk_step(const orc_cfg* c, int base, int m, double dt, double* qlo, dou
 
     for (int i = 0; i < ms; ++i) {
         /* Buffer rows and slow rows of the slow domain. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * (nzF + nzS)))
         for (int k = 0; k < nzS; ++k) {
             int in_b = (k >= b_lo && k < b_hi);
             for (int v = 0; v < NV; ++v)
@@ -603,7 +609,7 @@ int orc_mprk_step(const orc_cfg* c, int base, int m, double dt, double* qlo, dou
                 }
         }
         /* Fast partition. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * (nzF + nzS)))
         for (int k = 0; k < nzF; ++k)
             for (int v = 0; v < NV; ++v)
                 for (int x = 0; x < nx; ++x) {
@@ -624,7 +630,7 @@ int orc_mprk_step(const orc_cfg* c, int base, int m, double dt, double* qlo, dou
     }
 
     /* Completion, eq. MRK2-qn. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * (nzF + nzS)))
     for (int k = 0; k < nzF; ++k)
         for (int v = 0; v < NV; ++v)
             for (int x = 0; x < nx; ++x) {
@@ -633,7 +639,7 @@ int orc_mprk_step(const orc_cfg* c, int base, int m, double dt, double* qlo, dou
                 for (int i = 0; i < ms; ++i) acc += bF[i] * RF[(size_t)i * nF + id];
                 qF[id] = qF[id] + dt * acc;
             }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par_ok((size_t)nx * (nzF + nzS)))
     for (int k = 0; k < nzS; ++k) {
         int in_b = (k >= b_lo && k < b_hi);
         for (int v = 0; v < NV; ++v)

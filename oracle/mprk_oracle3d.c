@@ -53,6 +53,10 @@ typedef struct {
 int orc_tableau(int base, int m, double* aF, double* bF, double* cF, double* aB,
                 double* bB, double* cB, double* aS, double* bS, double* cS);
 
+/* Loops over fewer cells than this run on one thread (thread start-up would
+ * cost more; results do not depend on the thread count). */
+static inline int par3_ok(size_t cells) { return cells >= 16384; }
+
 static inline size_t ix3(int nx, int ny, int nz, int v, int k, int j, int i)
 {
     return (((size_t)v * (size_t)nz + (size_t)k) * (size_t)ny + (size_t)j) * (size_t)nx + (size_t)i;
@@ -153,7 +157,7 @@ static void domain_rhs3(const dom3_t* D, const double* q, const double* fvg, int
 #define DQ(d, v, k, j, i) dq[ix3(nx, ny, nz, (d) * N5 + (v), k, j, i)]
 #define DU(c, d, k, j, i) du[ix3(nx, ny, nz, (c) * 3 + (d), k, j, i)]
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)nz))
     for (int e = 0; e < ne; ++e) {
         int k = e - 1;
         int src = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
@@ -171,7 +175,7 @@ static void domain_rhs3(const dom3_t* D, const double* q, const double* fvg, int
 
     /* Cell gradients by central differences (the least-squares gradient on a
      * uniform grid, Appendix B footnote), using the ghost planes. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)nz))
     for (int k = 0; k < nz; ++k) {
         int e = k + 1;
         for (int j = 0; j < ny; ++j)
@@ -192,7 +196,7 @@ static void domain_rhs3(const dom3_t* D, const double* q, const double* fvg, int
     }
 
     /* x- and y-faces on the requested planes. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)nz))
     for (int k = k_lo; k < k_hi; ++k) {
         int e = k + 1;
         for (int j = 0; j < ny; ++j)
@@ -232,7 +236,7 @@ static void domain_rhs3(const dom3_t* D, const double* q, const double* fvg, int
     }
 
     /* z-faces f = k_lo .. k_hi (below plane f). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)nz))
     for (int f = k_lo; f <= k_hi; ++f) {
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -278,7 +282,7 @@ static void domain_rhs3(const dom3_t* D, const double* q, const double* fvg, int
     }
 
     /* Divergence plus source (0, 0, 0, rho g, rho w g). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)nz))
     for (int k = k_lo; k < k_hi; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -411,7 +415,7 @@ int orc3_mprk_step(const orc3_cfg* c, int base, int m, double dt, double* qlo, d
     double* Ssave = (double*)malloc(sizeof(double) * (size_t)s * nS);
 
     for (int i = 0; i < ms; ++i) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)(nzF + nzS)))
         for (int k = 0; k < nzS; ++k) {
             int in_b = (k >= b_lo && k < b_hi);
             for (int v = 0; v < N5; ++v)
@@ -431,7 +435,7 @@ int orc3_mprk_step(const orc3_cfg* c, int base, int m, double dt, double* qlo, d
                     }
                 }
         }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)(nzF + nzS)))
         for (int k = 0; k < nzF; ++k)
             for (int v = 0; v < N5; ++v)
                 for (size_t p = 0; p < pl; ++p) {
@@ -446,7 +450,7 @@ int orc3_mprk_step(const orc3_cfg* c, int base, int m, double dt, double* qlo, d
         if (c->fast_is_lower) coupled_rhs3(c, QF, QS, rF, rS, 0, nzF, s_lo, s_hi);
         else coupled_rhs3(c, QS, QF, rS, rF, s_lo, s_hi, 0, nzF);
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)(nzF + nzS)))
     for (int k = 0; k < nzF; ++k)
         for (int v = 0; v < N5; ++v)
             for (size_t p = 0; p < pl; ++p) {
@@ -455,7 +459,7 @@ int orc3_mprk_step(const orc3_cfg* c, int base, int m, double dt, double* qlo, d
                 for (int i = 0; i < ms; ++i) acc += bF[i] * RF[(size_t)i * nF + id];
                 qF[id] = qF[id] + dt * acc;
             }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (par3_ok(pl * (size_t)(nzF + nzS)))
     for (int k = 0; k < nzS; ++k) {
         int in_b = (k >= b_lo && k < b_hi);
         for (int v = 0; v < N5; ++v)
