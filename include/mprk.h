@@ -150,10 +150,18 @@ typedef struct mprk_ctx mprk_ctx;
 int mprk_validate(const mprk_config* cfg, char* msg, size_t len);
 
 /* Device workspace bytes a context needs for cfg (0 if cfg is invalid).
- * Host-only. */
+ * Host-only.  The workspace holds what one slow step of eq. (MRK2) keeps
+ * besides the state (Algorithm 1): the stage values of the base method
+ * (s-1 per domain, low-storage), the slow stage values that Algorithm 1
+ * copies to later stages (only the rows the buffer's stencil reads), the
+ * buffer's accumulated increments, and the reduction partials. */
 size_t mprk_workspace_bytes(const mprk_config* cfg);
 
-/* Create a context bound to caller-owned device memory.
+/* Create a context bound to caller-owned device memory: one instance of the
+ * coupled problem of Section 3, eq. (semi-discretized-coupled-model), with
+ * its partition into F, B and S (the index sets of the regions, Section 4)
+ * fixed by cfg (fast_is_lower, n_buffer) and the MPRK tableaux of eq. (MRK2)
+ * built from (base_rk, m) (Table 1 for base_rk = 2, m = 2).
  *   q_lower, q_upper : device state arrays (layout above), updated in place
  *                      by mprk_step / mprk_run.
  *   workspace        : device memory of at least mprk_workspace_bytes(cfg)
@@ -179,8 +187,11 @@ int mprk_rhs(mprk_ctx* ctx, const double* q_lower, const double* q_upper, double
  * context's stream; the state is updated in place.  Asynchronous. */
 int mprk_step(mprk_ctx* ctx, double dt);
 
-/* nsteps slow steps of size dt.  Every check_every steps (and after the last
- * one) runs the device reductions and synchronises the stream; returns
+/* nsteps slow steps of size dt (eq. MRK2 with the stage schedule of
+ * Algorithm 1, repeated).  Every check_every steps (and after the last
+ * one) runs the device reductions (the totals of Section 5.1, which are
+ * conserved when the buffer is long enough, Remark 1) and synchronises the
+ * stream; returns
  * MPRK_ENONFINITE at the first check that sees a bad state.  check_every <= 0
  * checks only after the last step.  If out != NULL it receives the stats of
  * the last check. */
@@ -202,15 +213,20 @@ int mprk_stable_dt(const mprk_config* cfg, const mprk_stats* st, double cr, doub
 /* Select the execution of later mprk_step / mprk_run calls (default
  * MPRK_EXEC_LAUNCH).  Both give bit-identical results: every cell is
  * computed by the same code from the same inputs.  The persistent mode needs
- * cooperative launch support (else mprk_run returns MPRK_EUNSUPPORTED); its
- * waits are bounded (2 s), so a run can end with MPRK_ETIMEOUT but never
- * hangs.  Kernel timing (mprk_profile_*) covers the launch mode only.  3D
+ * cooperative launch support (else mprk_run returns MPRK_EUNSUPPORTED).  Each
+ * persistent launch (one run segment between check points) is bounded in
+ * time: a tile that is still waiting for a neighbour once the launch has run
+ * longer than the limit of mprk_set_wait_limit aborts it, every workgroup
+ * then exits, and the run returns MPRK_ETIMEOUT.  Kernel timing (mprk_profile_*) covers the launch mode only.  3D
  * contexts support MPRK_EXEC_LAUNCH and MPRK_EXEC_GRAPH (MPRK_EXEC_PERSISTENT:
  * MPRK_EUNSUPPORTED). */
 int mprk_set_exec(mprk_ctx* ctx, int mode);
 
-/* Longest time (seconds, default 2) a tile of a persistent run waits for a
- * neighbour before the run is aborted with MPRK_ETIMEOUT. */
+/* Longest time (seconds, default 10) one persistent launch may run, counted
+ * from its start: a tile still waiting for a neighbour after that aborts the
+ * run with MPRK_ETIMEOUT (the state is then not a completed step).  The bound
+ * is on the launch, not on each wait, so a launch ends within the limit plus
+ * one tile's work.  0 aborts at the first wait that is not already met. */
 int mprk_set_wait_limit(mprk_ctx* ctx, double seconds);
 
 /* Tile shape of later launches (an mprk_tile value; default MPRK_TILE_32X16
@@ -228,7 +244,10 @@ int mprk_set_tile(mprk_ctx* ctx, int shape);
 int mprk_profile_enable(mprk_ctx* ctx, int on);
 int mprk_profile_take(mprk_ctx* ctx, double* kernel_ms, int64_t* launches);
 
-/* Release the context (not the caller's memory).  Synchronises its stream. */
+/* Release the context created by mprk_create (host memory only; not the
+ * caller's state, workspace or stream).  Synchronises its stream first, so
+ * the state holds the last completed step of eq. (MRK2).  NULL:
+ * MPRK_EINVAL. */
 int mprk_destroy(mprk_ctx* ctx);
 
 /* Static description of a status code. */

@@ -518,7 +518,7 @@ struct mprk_ctx {
     int ptiles_shape = -1;
     int pgrid = 0;                            // persistent grid size (0: recompute)
     int64_t wait_ticks = 0;
-    double wait_seconds = 2.0;
+    double wait_seconds = 10.0;
     std::vector<StageArgs> h_tab;             // host copies read by the async uploads
     std::vector<TileRef> h_tiles;
     MemberRun h_mr;
@@ -566,7 +566,7 @@ struct mprk_batch {
     std::vector<int32_t> h_slots;
     int pgrid = 0, pgrid_shape = -1;
     int64_t wait_ticks = 0;
-    double wait_seconds = 2.0;
+    double wait_seconds = 10.0;
     StepGraph graph;
     int graph_shape = -1;
     std::vector<std::vector<void*>> g_args;   // per node: pointers to its argument values
@@ -724,7 +724,7 @@ int run_persistent(mprk_ctx* c, double dt, int64_t nsteps)
     P.abort_flag = done + ntiles;
     P.ntiles = ntiles;
     P.gmax = (int32_t)(nsteps * ms);
-    P.wait_ticks = c->wait_ticks;
+    P.run_ticks = c->wait_ticks;
     if (launch_persistent(P, c->pgrid, g.flux_bits == 32, c->shape, c->stream) != hipSuccess)
         return MPRK_EHIP;
     return MPRK_OK;
@@ -1025,7 +1025,7 @@ int batch_persistent(mprk_batch* b, int64_t nsteps)
     P.abort_flag = done + ntiles;
     P.ntiles = ntiles;
     P.gmax = (int32_t)(nsteps * b->nslots);
-    P.wait_ticks = b->wait_ticks;
+    P.run_ticks = b->wait_ticks;
     if (launch_persistent(P, b->pgrid, b->flux32, b->shape, b->stream) != hipSuccess) return MPRK_EHIP;
     return MPRK_OK;
 }

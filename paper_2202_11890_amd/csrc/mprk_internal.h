@@ -147,10 +147,11 @@ struct PersistArgs {
     const TileRef* tiles;      // every fixed tile of every member
     const MemberRun* members;
     int32_t* done;             // progress counters, zero before the launch
-    int32_t* abort_flag;       // set (never cleared by the kernel) if a wait timed out
+    int32_t* abort_flag;       // set (never cleared by the kernel) if the launch timed out
     int32_t ntiles;
     int32_t gmax;              // stages of the launch: nslots * nsteps
-    int64_t wait_ticks;        // longest a task may wait, in wall-clock ticks
+    int64_t run_ticks;         // longest the launch may run, in wall-clock ticks: a tile
+                               // still waiting for a neighbour after that aborts it
 };
 
 // Batched launches: the blocks of one launch are split into consecutive

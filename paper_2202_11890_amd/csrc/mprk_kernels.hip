@@ -559,9 +559,14 @@ void batch_kernel(const StageArgs* __restrict__ tab, const BatchEntry* __restric
 // neighbours (x periodic) and, next to the interface, the tile across it.
 // Called by the whole of wave 0: lane l < 9 polls neighbour (l%3 - 1, l/3 - 1),
 // lane 9 the interface partner, all in parallel; a wave-wide vote decides.
-// Returns false on timeout or abort; the kernel then exits without
-// finishing (bounded: it never hangs).
-__device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const TileRef& tr, int g)
+// Returns false once the launch has run longer than its limit (counted from
+// t_start, this workgroup's start, which for a cooperative launch is the
+// launch's start) or another workgroup has aborted; the kernel then exits
+// without finishing.  The limit is on the whole launch, not on each wait, so
+// however many waits a workgroup makes, it exits within the limit plus one
+// tile's work.
+__device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const TileRef& tr, int g,
+                            int64_t t_start)
 {
     const int need = g - 1;
     if (need <= 0) return true;
@@ -579,7 +584,6 @@ __device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const Tile
         if (tr.dom == 0 && tr.tz == tzmax) dep = M.done_base[1] + tr.tx;
         if (tr.dom == 1 && tr.tz == 0) dep = M.done_base[0] + (M.tiles_z[0] - 1) * M.tiles_x + tr.tx;
     }
-    const int64_t t0 = wall_clock64();
     while (true) {
         const bool ready = dep < 0 ||
             __hip_atomic_load(P.done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
@@ -587,7 +591,7 @@ __device__ bool wait_inputs(const PersistArgs& P, const MemberRun& M, const Tile
         __builtin_amdgcn_s_sleep(1);
         const bool ab = lane == 0 &&
             __hip_atomic_load(P.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        if (__any(ab) || wall_clock64() - t0 > P.wait_ticks) {
+        if (__any(ab) || wall_clock64() - t_start > P.run_ticks) {
             if (lane == 0) __hip_atomic_store(P.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
@@ -607,6 +611,7 @@ void persistent_kernel(const PersistArgs P)
 {
     __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
     __shared__ int s_go;
+    const int64_t t_start = wall_clock64();
     const int G = gridDim.x;
     for (int g = 1; g <= P.gmax; ++g) {
         // Blocks j and j + G run on the same XCD when G % 8 == 0; the remap
@@ -623,7 +628,7 @@ void persistent_kernel(const PersistArgs P)
             const bool work = rec >= 0 && D.row_hi > D.row_lo && z0 < D.row_hi && z0 + S::TZ > D.row_lo;
             if (work) {
                 if (threadIdx.x < 64) {
-                    const bool ok = wait_inputs(P, M, tr, g);
+                    const bool ok = wait_inputs(P, M, tr, g, t_start);
                     if (threadIdx.x == 0) s_go = ok ? 1 : 0;
                 }
                 __syncthreads();

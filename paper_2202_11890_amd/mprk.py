@@ -18,9 +18,8 @@ TILE_NAMES = ("32x16", "16x32", "64x8", "32x8")
 REGION_F, REGION_B, REGION_S, REGION_ALL = 1, 2, 4, 7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# MPRK_LIB selects another build of the same library (side-by-side variants);
-# by default the in-tree build next to this file is used.
-LIB_PATH = os.environ.get("MPRK_LIB") or os.path.join(_HERE, "libmprk.so")
+# Always the in-tree build next to this file.
+LIB_PATH = os.path.join(_HERE, "libmprk.so")
 
 
 class mprk_config(ctypes.Structure):

@@ -7,8 +7,9 @@ resident in device memory and advances all of them together as one batch
 finished requests leave (their state is copied to pinned host memory on a
 copy stream while the next chunk runs, and their memory is released when the
 copy completes) and requests that have arrived are admitted while the device
-memory budget (state + workspace share, ``mprk_batch_workspace_bytes``) and
-the slot count allow, so new work joins work already on the device.
+memory budget (the states held, plus the workspace of the batch that the
+admission would make, ``mprk_batch_workspace_bytes``) and the slot count
+allow, so new work joins work already on the device.
 
 A request's arithmetic is that of a batch member: it does not depend on what
 else is in the batch or on how its steps are split into chunks (each member
@@ -57,12 +58,31 @@ class Result:
         return self.finished - self.arrival
 
 
+def state_bytes(cfg) -> int:
+    """Device bytes of a request's two state arrays."""
+    return 8 * 4 * cfg.nx * (cfg.nz_lower + cfg.nz_upper)
+
+
+def batch_bytes(cfgs) -> int:
+    """Device bytes of the workspace of a batch of these configurations, as
+    mprk.Batch allocates it (mprk_batch_workspace_bytes plus alignment
+    slack).  A batch's workspace is not the sum of its members' one-member
+    workspaces (its launch tables grow with the largest m*s times the number
+    of members), so admission asks for the whole prospective batch."""
+    if not cfgs:
+        return 0
+    probes = []
+    base = 1 << 20
+    for cfg in cfgs:
+        n = state_bytes(cfg)
+        probes.append(mprk.mprk_member(cfg, base, base + n // 2, 1.0))
+        base += n
+    return mprk.mprk_batch_workspace_bytes(probes) + 256
+
+
 def footprint(cfg) -> int:
-    """Device bytes a request holds while admitted: its two state arrays plus
-    its share of a batch workspace (the workspace of a one-member batch)."""
-    state = 8 * 4 * cfg.nx * (cfg.nz_lower + cfg.nz_upper)
-    probe = mprk.mprk_member(cfg, 1 << 20, (1 << 20) + state, 1.0)
-    return state + mprk.mprk_batch_workspace_bytes([probe])
+    """Device bytes of a request alone: its states and a one-member batch."""
+    return state_bytes(cfg) + batch_bytes([cfg])
 
 
 class _Active:
@@ -101,9 +121,11 @@ class Server:
         self.batch = None
         self.dirty = False
         self.active: List[_Active] = []
-        self.used = 0
+        self.used = 0                # state bytes of admitted and outgoing requests
+        self.ws_bytes = 0            # workspace bytes of the current batch
         self.rebuilds = 0
-        self.log = []                # (time, active count, bytes held) after each chunk
+        self.log = []                # (time, active count, device bytes held: states and
+                                     # the batch workspace) after each chunk
         # host seconds spent admitting (copies in), rebuilding the batch (with
         # the step rule of new requests), running chunks and retiring (copies out)
         self.seconds = {"admit": 0.0, "rebuild": 0.0, "run": 0.0, "retire": 0.0}
@@ -117,9 +139,11 @@ class Server:
         if self.batch is not None:
             self.batch.close()
             self.batch = None
+        self.ws_bytes = 0
         if self.active:
             self.batch = mprk.Batch([(a.req.cfg, a.ql, a.qu, a.dt if a.dt is not None else 1.0)
                                      for a in self.active], exec_mode=self.exec_mode, tile=self.tile)
+            self.ws_bytes = batch_bytes([a.req.cfg for a in self.active])
             self.rebuilds += 1
             # Step rule for requests admitted without one, from their initial
             # state: one batched reduction for all of them (each member's
@@ -181,8 +205,12 @@ class Server:
             ta = self.clock()
             while pending and pending[0].arrival <= now and len(self.active) < self.max_slots:
                 r = pending[0]
-                need = footprint(r.cfg)
-                if self.used + need > self.budget:
+                need = state_bytes(r.cfg)
+                # The new states are allocated while the current batch (and
+                # its workspace) still exists; the rebuild then frees that
+                # workspace before allocating the new batch's.
+                ws = batch_bytes([a.req.cfg for a in self.active] + [r.cfg])
+                if self.used + need + max(ws, self.ws_bytes) > self.budget:
                     break
                 pending.pop(0)
                 ql = torch.from_numpy(np.ascontiguousarray(r.q_lower)).to(self.device)
@@ -235,7 +263,7 @@ class Server:
                 self.active = keep
                 self.dirty = True
             self.seconds["retire"] += self.clock() - tr
-            self.log.append((self.clock() - t0, len(self.active), self.used))
+            self.log.append((self.clock() - t0, len(self.active), self.used + self.ws_bytes))
         if self.batch is not None:
             self.batch.close()
             self.batch = None

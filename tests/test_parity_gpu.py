@@ -194,18 +194,33 @@ def test_run_matches_oracle(name, w, n):
     assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
 
 
-def test_large_fifty_steps_matches_oracle():
-    """The 1024 x 512 workload, 50 slow steps (the oracle takes 10-30 s)."""
+def test_large_two_hundred_steps_matches_oracle():
+    """The 1024 x 512 workload in the benchmark's launch configuration, 200
+    slow steps (a fifth of the benchmark run; the oracle takes about a minute
+    on 16 host threads, in chunks of 50 steps, restarts being bitwise),
+    compared after 50 and after 200 steps."""
     w = inputs.large()
-    say("run large 50 steps")
+    say("run large 200 steps")
     ql, qu = inputs.initial_state(w)
-    dt = oracle.dt_rule(problem_of(w), ql, qu, w.m)
-    (gl, gu), st = run_gpu(w, ql, qu, dt, 50)
-    assert st["status"] == 0 and st["steps_done"] == 50
-    ol, ou = run_oracle(w, ql, qu, dt, 50)
-    el, eu = state_err(gl, ol), state_err(gu, ou)
-    say("  err lower", el, "upper", eu)
-    assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
+    pb = problem_of(w)
+    dt = oracle.dt_rule(pb, ql, qu, w.m)
+    tl, tu = dev(ql), dev(qu)
+    sol = mprk.Solver(mprk.config_of_workload(w), tl, tu)
+    ol, ou = ql.copy(), qu.copy()
+    done = 0
+    for upto in (50, 200):
+        st = sol.run(dt, upto - done, check_every=10)
+        torch.cuda.synchronize()
+        assert st["status"] == 0 and st["steps_done"] == upto
+        gl, gu = tl.cpu().numpy(), tu.cpu().numpy()
+        while done < upto:
+            oracle.mprk_run(pb, w.base, w.m, dt, 50, ol, ou)
+            done += 50
+            say("  oracle", done, "steps")
+        el, eu = state_err(gl, ol), state_err(gu, ou)
+        say("  after", upto, "steps: err lower", el, "upper", eu)
+        assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
+    sol.close()
 
 
 @pytest.mark.skipif(not os.environ.get("MPRK_LONG_PARITY"),

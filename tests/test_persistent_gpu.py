@@ -78,9 +78,9 @@ def test_persistent_matches_oracle():
 
 
 def test_persistent_timeout_is_reported_and_recoverable():
-    """A zero wait limit makes the first wait abort the run: every workgroup
-    exits and the call returns MPRK_ETIMEOUT; a later run with the normal
-    limit is correct again."""
+    """A zero limit on the launch's run time makes the first wait that is not
+    already met abort the run: every workgroup exits and the call returns
+    MPRK_ETIMEOUT; a later run with the normal limit is correct again."""
     w = inputs.large()
     ql, qu = inputs.initial_state(w)
     dt = oracle.dt_rule(problem_of(w), ql, qu, w.m)
@@ -91,7 +91,7 @@ def test_persistent_timeout_is_reported_and_recoverable():
     with pytest.raises(mprk.MprkError) as e:
         sol.run(dt, 2)
     assert e.value.code == mprk.ETIMEOUT
-    sol.set_wait_limit(2.0)
+    sol.set_wait_limit(10.0)
     tl.copy_(torch.from_numpy(ql))
     tu.copy_(torch.from_numpy(qu))
     sol.run(dt, 2)

@@ -42,7 +42,22 @@ def test_served_results_equal_alone(flux_bits):
     reqs = requests(flux_bits)
     budget = 3 * max(serving.footprint(r.cfg) for r in reqs)
     srv = serving.Server(DEV, budget, max_slots=4, chunk=7)
+    held = []
+    real_rebuild = srv._rebuild
+
+    def rebuild():
+        # Device bytes really held right after each rebuild: the admitted
+        # requests' states plus the new batch's workspace tensor.
+        real_rebuild()
+        states = sum(a.ql.numel() * 8 + a.qu.numel() * 8 for a in srv.active)
+        states += sum(o[0].ql.numel() * 8 + o[0].qu.numel() * 8 for o in srv.outgoing)
+        ws = srv.batch.workspace.numel() if srv.batch is not None else 0
+        assert ws == srv.ws_bytes
+        held.append(states + ws)
+
+    srv._rebuild = rebuild
     res = {r.rid: r for r in srv.run(reqs)}
+    assert held and max(held) <= budget
     assert sorted(res) == [r.rid for r in reqs]
     assert max(n for _, n, _ in srv.log) >= 2          # requests shared the device
     assert max(u for _, _, u in srv.log) <= budget

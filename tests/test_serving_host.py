@@ -120,3 +120,25 @@ def test_chunks_end_exactly_at_each_step_count(fake):
     # first four departures
     assert len(srv.log) == 5 and [n for _, n, _ in srv.log] == [4, 3, 2, 1, 0]
     assert srv.rebuilds == 5 == len(fake.made)
+
+
+def test_admission_charges_the_whole_batch_workspace(fake):
+    """A batch's workspace grows with its largest m*s times its member count,
+    so a mix of members with different m needs more than the sum of their
+    one-member footprints; admission charges the workspace of the batch it
+    would create.  With a budget of exactly the summed footprints of a mix,
+    the whole mix is not admitted at once, and after every chunk the states
+    plus the batch workspace stay within the budget."""
+    reqs = []
+    for i, m in enumerate([2, 8, 2, 8, 2, 8]):
+        w = inputs.small().with_(nx=256, nz_lower=64, nz_upper=64, m=m, seed=700 + i)
+        ql, qu = inputs.initial_state(w)
+        reqs.append(serving.Request(i, mprk.config_of_workload(w), ql, qu, 3, 0.0, 0.01))
+    summed = sum(serving.footprint(r.cfg) for r in reqs)
+    whole = sum(serving.state_bytes(r.cfg) for r in reqs) + serving.batch_bytes([r.cfg for r in reqs])
+    assert whole > summed                       # the overshoot a per-member charge would allow
+    srv = serving.Server("cpu", summed, max_slots=16, chunk=3)
+    res = srv.run(reqs)
+    assert len(res) == len(reqs)
+    assert max(n for _, n, _ in srv.log) < len(reqs)
+    assert max(u for _, _, u in srv.log) <= summed
