@@ -202,6 +202,29 @@ int mprk_run(mprk_ctx* ctx, double dt, int64_t nsteps, int64_t check_every, mprk
  * state is bad (out is still filled). */
 int mprk_diagnostics(mprk_ctx* ctx, mprk_stats* out);
 
+/* Allocation-free variant of mprk_diagnostics, for callers that cannot
+ * allocate device memory or create a context (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Runs the same
+ * device reductions (the same kernels, so the same bits as mprk_diagnostics)
+ * on the given device states q_lower / q_upper (layout as above, dim 2 or 3)
+ * for the configuration cfg (checked as by mprk_validate), on hip_stream
+ * (NULL: the null stream), and synchronises that stream.  out (optional)
+ * receives the stats; steps_done is 0.  Returns MPRK_ENONFINITE for a bad
+ * state (out is still filled), MPRK_EINVAL / MPRK_EBUFFER /
+ * MPRK_EUNSUPPORTED for a configuration mprk_validate rejects, MPRK_EHIP on
+ * a HIP error.
+ * Scratch: the reduction partials live in a file-scope device array of the
+ * library, 57,568 bytes per device (2 domains x 256 partial blocks x 14
+ * fields, then 2 x 14 final fields, FP64), held by every device the library
+ * runs on until the process ends.  The need does not depend on the problem
+ * size: any size mprk_validate accepts fits.  The call allocates nothing
+ * (no hipMalloc, no workspace, no context).  Every call on one device shares
+ * that device's array: calls that overlap on one device (two host threads,
+ * or two streams without ordering between them) race and give wrong stats;
+ * callers must serialise them. */
+int mprk_diagnostics_static(const mprk_config* cfg, const double* q_lower, const double* q_upper,
+                            void* hip_stream, mprk_stats* out);
+
 /* Stable slow step from stats (host-only).  Per domain the step limit is
  * 1 / (lambda/cr + visc/dn) (advective and diffusive limits combined); the
  * slow step is min(m * fast-domain limit, slow-domain limit).  Returns

@@ -354,14 +354,14 @@ StageArgs proxy_args(const Member& mb, double dt, int k, int j, int shape)
     return a;
 }
 
-// Reduction record of one member (partials in its scratch; finals at final_).
-ReduceArgs member_reduce_args(const Member& mb, double* final_)
+// Reduction record of a state pair (partials and finals where given).
+ReduceArgs reduce_args(const mprk_config& g, const double* q_lower, const double* q_upper,
+                       double* partial, double* final_)
 {
-    const mprk_config& g = mb.cfg;
     ReduceArgs r;
     std::memset(&r, 0, sizeof r);
-    r.q[0] = mb.q[0];
-    r.q[1] = mb.q[1];
+    r.q[0] = q_lower;
+    r.q[1] = q_upper;
     r.nz[0] = g.nz_lower;
     r.nz[1] = g.nz_upper;
     r.nx = g.nx;
@@ -377,9 +377,15 @@ ReduceArgs member_reduce_args(const Member& mb, double* final_)
     r.visc_coef[1] = coef * g.mu_upper * (1.0 / (g.dx * g.dx) + hy + 1.0 / (g.dz_upper * g.dz_upper));
     r.gamma = g.gamma;
     r.gm1 = g.gamma - 1.0;
-    r.partial = (double*)(mb.ws + mb.lay.off_partial);
+    r.partial = partial;
     r.final_ = final_;
     return r;
+}
+
+// Reduction record of one member (partials in its scratch; finals at final_).
+ReduceArgs member_reduce_args(const Member& mb, double* final_)
+{
+    return reduce_args(mb.cfg, mb.q[0], mb.q[1], (double*)(mb.ws + mb.lay.off_partial), final_);
 }
 
 // Device reductions of one member: totals, stability measures, status.
@@ -394,9 +400,8 @@ int member_reduce_launch(const Member& mb, hipStream_t stream, double* host_fina
 }
 
 // Stats from the reduced fields (after the stream is synchronised).
-int member_stats(const Member& mb, const double* host_final, int64_t steps, mprk_stats* out)
+int stats_from_final(const mprk_config& g, const double* host_final, int64_t steps, mprk_stats* out)
 {
-    const mprk_config& g = mb.cfg;
     mprk_stats st;
     std::memset(&st, 0, sizeof st);
     const double dy = g.dim == 3 ? g.dy : 1.0;
@@ -416,6 +421,11 @@ int member_stats(const Member& mb, const double* host_final, int64_t steps, mprk
     st.status = bad;
     if (out) *out = st;
     return bad ? MPRK_ENONFINITE : MPRK_OK;
+}
+
+int member_stats(const Member& mb, const double* host_final, int64_t steps, mprk_stats* out)
+{
+    return stats_from_final(mb.cfg, host_final, steps, out);
 }
 
 // Device properties needed by the persistent mode.
@@ -1342,6 +1352,29 @@ int mprk_diagnostics(mprk_ctx* c, mprk_stats* out)
 {
     if (!c) return MPRK_EINVAL;
     return run_reduce(c, out);
+}
+
+int mprk_diagnostics_static(const mprk_config* cfg, const double* q_lower, const double* q_upper,
+                            void* hip_stream, mprk_stats* out)
+{
+    const int rc = mprk_validate(cfg, nullptr, 0);
+    if (rc != MPRK_OK) return rc;
+    if (!q_lower || !q_upper) return MPRK_EINVAL;
+    if (((uintptr_t)q_lower | (uintptr_t)q_upper) % sizeof(double)) return MPRK_EINVAL;
+    // The scratch need is fixed (partials of a fixed block count, then the
+    // finals) whatever the size mprk_validate accepted.
+    static_assert(STATIC_SCRATCH_DOUBLES >= (size_t)2 * RED_BLOCKS * RED_FIELDS + 2 * RED_FIELDS,
+                  "scratch holds the partials and the finals");
+    double* scr = nullptr;
+    if (static_scratch_address(&scr) != hipSuccess) return MPRK_EHIP;
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    const ReduceArgs r = reduce_args(*cfg, q_lower, q_upper, scr, scr + (size_t)2 * RED_BLOCKS * RED_FIELDS);
+    if (launch_reduce(r, stream) != hipSuccess) return MPRK_EHIP;
+    double host_final[2 * RED_FIELDS];
+    if (hipMemcpyAsync(host_final, r.final_, sizeof host_final, hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return MPRK_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return MPRK_EHIP;
+    return stats_from_final(*cfg, host_final, 0, out);
 }
 
 int mprk_run(mprk_ctx* c, double dt, int64_t nsteps, int64_t check_every, mprk_stats* out)

@@ -179,6 +179,12 @@ hipError_t launch_persistent(const PersistArgs& a, int grid, bool flux32, int sh
 hipError_t launch_fill_i32(int32_t* p, int32_t value, int n, hipStream_t s);
 int persistent_blocks_per_cu(bool flux32, int shape);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+
+// Doubles of the file-scope device scratch of the allocation-free
+// diagnostics (partials, then finals); the need does not depend on the
+// problem size (the reduction is grid-stride over a fixed block count).
+constexpr size_t STATIC_SCRATCH_DOUBLES = (size_t)2 * RED_BLOCKS * RED_FIELDS + (size_t)2 * RED_FIELDS;
+hipError_t static_scratch_address(double** out);
 // 3D stage kernel (one tile shape per flux type).
 hipError_t launch_stage3(const StageArgs& a, hipStream_t s);
 KernelRef stage3_kernel_ref(bool flux32);

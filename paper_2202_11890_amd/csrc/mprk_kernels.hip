@@ -23,6 +23,8 @@
 //
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
 // stability measures and the physical-state flag.
+#include <mutex>
+
 #include "mprk_internal.h"
 #include "mprk_device.h"
 
@@ -906,6 +908,42 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_final, dim3(2), dim3(RED_THREADS), 0, s, a);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reduction scratch of the allocation-free diagnostics entry point: the
+// partial results of reduce_partial ([2][RED_BLOCKS][RED_FIELDS]) followed by
+// the final fields ([2][RED_FIELDS]).  One copy per device, held until the
+// process ends; every call on a device shares it.  reduce_partial writes
+// every partial slot before reduce_final reads it, so nothing needs clearing
+// between calls.
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int STATIC_SCRATCH_MAX_DEVICES = 64;
+std::mutex static_scratch_mu;
+double* static_scratch_ptr[STATIC_SCRATCH_MAX_DEVICES];
+}  // namespace
+
+// Device address of the scratch array on the current device.  The name
+// `scratch` is a host-side stand-in in host code, so the address is looked up
+// (once per device, with that device current) and kept.
+hipError_t static_scratch_address(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= STATIC_SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(static_scratch_mu);
+    if (!static_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        static_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = static_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace mprk

@@ -88,7 +88,8 @@ class mprk_member(ctypes.Structure):
 
 
 EXPORTS = ("mprk_validate", "mprk_workspace_bytes", "mprk_create", "mprk_set_stream", "mprk_rhs",
-           "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_stable_dt", "mprk_set_exec",
+           "mprk_step", "mprk_run", "mprk_diagnostics", "mprk_diagnostics_static", "mprk_stable_dt",
+           "mprk_set_exec",
            "mprk_set_wait_limit", "mprk_set_tile",
            "mprk_profile_enable", "mprk_profile_take", "mprk_destroy", "mprk_strerror",
            "mprk_batch_validate", "mprk_batch_workspace_bytes", "mprk_batch_create",
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.mprk_step.argtypes = [V, ctypes.c_double]
     lib.mprk_run.argtypes = [V, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, S]
     lib.mprk_diagnostics.argtypes = [V, S]
+    lib.mprk_diagnostics_static.argtypes = [C, V, V, V, S]
     lib.mprk_stable_dt.argtypes = [C, S, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_double)]
     lib.mprk_set_exec.argtypes = [V, ctypes.c_int]
@@ -198,6 +200,14 @@ def mprk_run(ctx, dt, nsteps, check_every):
 def mprk_diagnostics(ctx):
     st = mprk_stats()
     rc = load().mprk_diagnostics(ctx, ctypes.byref(st))
+    return rc, st
+
+
+def mprk_diagnostics_static(cfg, q_lower_ptr, q_upper_ptr, stream_ptr):
+    """Allocation-free diagnostics of a state pair (no context, no workspace)."""
+    st = mprk_stats()
+    rc = load().mprk_diagnostics_static(ctypes.byref(cfg), q_lower_ptr, q_upper_ptr, stream_ptr,
+                                        ctypes.byref(st))
     return rc, st
 
 
