@@ -270,3 +270,20 @@ def test_counter_profiles_are_reported_only_for_the_kernels_they_measured():
             assert got == d["hbm_bytes_per_launch"]
         else:
             assert got is None
+
+
+def test_time_at_error_interpolates_in_log_log():
+    """The benchmark's equal-error helper: time along a power law is
+    recovered exactly between runs, a target coarser than the coarsest run
+    costs that run's time, a finer one is extrapolated along the two finest."""
+    import bench
+
+    k = np.array([1.0, 2.0, 4.0, 8.0])
+    errors = 3e-4 / k ** 2          # second order: error ~ dt^2, time ~ 1/dt
+    times = 0.5 * k
+    t, how = bench.time_at_error(errors, times, 3e-4 / 3.0 ** 2)
+    assert how == "interpolated" and t == pytest.approx(1.5, rel=1e-12)
+    t, how = bench.time_at_error(errors, times, 1e-3)
+    assert how == "capped" and t == 0.5
+    t, how = bench.time_at_error(errors, times, 3e-4 / 16.0 ** 2)
+    assert how == "extrapolated" and t == pytest.approx(8.0, rel=1e-12)
