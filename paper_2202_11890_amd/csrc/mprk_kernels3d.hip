@@ -588,25 +588,555 @@ __global__ __launch_bounds__(TileOf<FT>::S::NT) void stage_kernel3(const StageAr
     else stage_tile3<1, FT>(A, t, smem);
 }
 
+// ---------------------------------------------------------------------------
+// z-marching stage kernel (used with FP32 face fluxes).  A workgroup owns a
+// TX x TY block of columns and one segment of LZ planes of a domain and walks
+// the segment upward, one plane per step.  LDS holds a two-plane ring of the
+// staged state (2-cell x-y halo), a three-plane ring of the primitives
+// u, v, w, T (1-cell halo) and the x-y flux exchange; each thread keeps its
+// own column's state at planes z-1 .. z+2 in registers.  Per plane: the x and
+// y faces of the plane come from the staged plane; the z-face above it from
+// the column registers; the z-face below it is the one computed at the
+// previous plane (only a segment's first plane computes its lower face).  A
+// plane is staged once per segment (the brick kernel staged each cell of a
+// 2-plane z-halo for every 4-plane tile), and the next plane's global loads
+// are in flight while the current one is computed.
+template <int X, int Y, int L>
+struct MShape {
+    static constexpr int TX = X, TY = Y, LZ = L, NT = X * Y;
+    static constexpr int HX = X + 4, HY = Y + 4, QPL = HX * HY;   // staged plane, 2-cell halo
+    static constexpr int PX = X + 2, PY = Y + 2, PPL = PX * PY;   // primitive plane, 1-cell halo
+    static constexpr int EXX = Y * (X + 1), EXY = (Y + 1) * X;    // x-y flux exchange
+    static constexpr int NPOS = (QPL + NT - 1) / NT;              // staged positions per thread
+    static constexpr int LDS_Q = 2 * NV3 * QPL;
+    static constexpr int LDS_P = 3 * 4 * PPL;
+    static constexpr int LDS_X = NV3 * (EXX + EXY);
+    static_assert(NT % 64 == 0 && NT <= 1024 && NT >= 64 + X && Y <= 64, "marching tile shape");
+    template <class FT>
+    static constexpr int lds_bytes() { return (LDS_Q + LDS_P + LDS_X) * (int)sizeof(FT) + 3 * X * Y * 8; }
+};
+
+#ifndef MPRK3_MARCH_TX
+#define MPRK3_MARCH_TX 32
+#endif
+#ifndef MPRK3_MARCH_TY
+#define MPRK3_MARCH_TY 8
+#endif
+#ifndef MPRK3_MARCH_LZ
+#define MPRK3_MARCH_LZ 16
+#endif
+#ifndef MPRK3_MARCH_WAVES
+#define MPRK3_MARCH_WAVES 3
+#endif
+using M32 = MShape<MPRK3_MARCH_TX, MPRK3_MARCH_TY, MPRK3_MARCH_LZ>;
+
+// Inviscid LLF flux of a face in its normal frame from the reconstructed
+// states qL, qR (face frame: rho, normal, tangential 1, tangential 2,
+// energy); mirror kinds as in face3, whose arithmetic this repeats, so a face
+// evaluated by two tiles obtains the same bits from the same inputs.
+template <class FT>
+__device__ __forceinline__ void llf3n(const StageArgs& A, FT qL[NV3], FT qR[NV3], int kind, FT Fn[NV3])
+{
+#pragma clang fp contract(off)
+    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT h = FT(0.5);
+    if (kind == F3_TOP) {
+        qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3]; qR[4] = qL[4];
+    } else if (kind == F3_BOTTOM) {
+        qL[0] = qR[0]; qL[1] = -qR[1]; qL[2] = qR[2]; qL[3] = qR[3]; qL[4] = qR[4];
+    }
+    const FT yL = Fm<FT>::rsqrt(qL[0]), yR = Fm<FT>::rsqrt(qR[0]);
+    const FT rL = yL * yL, rR = yR * yR;
+    const FT sL = qL[0] * yL, sR = qR[0] * yR;
+    const FT unL = qL[1] * rL, a1L = qL[2] * rL, a2L = qL[3] * rL;
+    const FT unR = qR[1] * rR, a1R = qR[2] * rR, a2R = qR[3] * rR;
+    const FT pL = gm1 * fma(-h, fma(qL[1], unL, fma(qL[2], a1L, qL[3] * a2L)), qL[4]);
+    const FT pR = gm1 * fma(-h, fma(qR[1], unR, fma(qR[2], a1R, qR[3] * a2R)), qR[4]);
+    const FT aL = Fm<FT>::ws_sqrt(gamma * pL * rL);
+    const FT aR = Fm<FT>::ws_sqrt(gamma * pR * rR);
+    const FT iw = Fm<FT>::ws_rcp(sL + sR);
+    const FT unr = fma(sL, unL, sR * unR) * iw;
+    const FT a1r = fma(sL, a1L, sR * a1R) * iw;
+    const FT a2r = fma(sL, a2L, sR * a2R) * iw;
+    const FT HL = (qL[4] + pL) * rL, HR = (qR[4] + pR) * rR;
+    const FT Hr = fma(sL, HL, sR * HR) * iw;
+    const FT ar = Fm<FT>::ws_sqrt(gm1 * fma(-h, fma(unr, unr, fma(a1r, a1r, a2r * a2r)), Hr));
+    const FT lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
+    if (kind != F3_INTERIOR) {
+        Fn[0] = FT(0);
+        Fn[1] = (kind == F3_TOP) ? fma(lam, qL[1], fma(qL[1], unL, pL)) : fma(-lam, qR[1], fma(qR[1], unR, pR));
+        Fn[2] = FT(0);
+        Fn[3] = FT(0);
+        Fn[4] = FT(0);
+        return;
+    }
+    const FT hl = h * lam;
+    Fn[0] = fma(-hl, qR[0] - qL[0], h * (qL[1] + qR[1]));
+    Fn[1] = fma(-hl, qR[1] - qL[1], h * (fma(qL[1], unL, qR[1] * unR) + (pL + pR)));
+    Fn[2] = fma(-hl, qR[2] - qL[2], h * fma(qL[2], unL, qR[2] * unR));
+    Fn[3] = fma(-hl, qR[3] - qL[3], h * fma(qL[3], unL, qR[3] * unR));
+    Fn[4] = fma(-hl, qR[4] - qL[4], h * fma(qL[4] + pL, unL, (qR[4] + pR) * unR));
+}
+
+// Viscous part of an interior face (Appendix B: common velocity, normal
+// derivatives by finite difference, tangential ones by averaging the cell
+// gradients), subtracted from the inviscid flux Fn in the face frame.
+template <class FT, int dir>
+__device__ __forceinline__ void visc3n(const DomainArgs& D, const FT uh[3], const FT g[3][3], FT Tn, FT Fn[NV3])
+{
+#pragma clang fp contract(off)
+    constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;
+    const FT mu = FT(D.mu);
+    FT sg[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        sg[c] = (c == dir) ? mu * fma(FT(4.0 / 3.0), g[dir][dir], FT(-2.0 / 3.0) * (g[t1][t1] + g[t2][t2]))
+                           : mu * (g[dir][c] + g[c][dir]);
+    const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], FT(D.kappa) * Tn)));
+    Fn[1] = Fn[1] - sg[dir];
+    Fn[2] = Fn[2] - sg[t1];
+    Fn[3] = Fn[3] - sg[t2];
+    Fn[4] = Fn[4] - en;
+}
+
+// Face frame -> (rho, rho u, rho v, rho w, rho E).
+template <class FT, int dir>
+__device__ __forceinline__ void from_frame(const FT Fn[NV3], FT F[NV3])
+{
+    constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;
+    F[0] = Fn[0];
+    F[1 + dir] = Fn[1];
+    F[1 + t1] = Fn[2];
+    F[1 + t2] = Fn[3];
+    F[4] = Fn[4];
+}
+
+// x- (dir 0) or y-face (dir 1) between staged-plane cell (x, y) and its +dir
+// neighbour.  Q: the plane's state slot [5][HY][HX]; Pm, P0, Pp: primitive
+// slots [4][PY][PX] of planes z-1, z, z+1.
+template <class FT, int dir, class S>
+__device__ __forceinline__ void face_xy(const StageArgs& A, const DomainArgs& D, const FT* Q, const FT* Pm,
+                                        const FT* P0, const FT* Pp, int x, int y, FT F[NV3])
+{
+#pragma clang fp contract(off)
+    constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;
+    constexpr int comp[NV3] = {0, 1 + dir, 1 + t1, 1 + t2, 4};
+    constexpr int sn = dir == 0 ? 1 : S::HX;
+    const FT q4 = FT(0.25), h = FT(0.5);
+    FT qL[NV3], qR[NV3];
+    const int qb = (y + 2) * S::HX + x + 2;
+#pragma unroll
+    for (int k = 0; k < NV3; ++k) {
+        const FT* s = Q + comp[k] * S::QPL + qb;
+        const FT qm = s[-sn], q0 = s[0], q1 = s[sn], q2 = s[2 * sn];
+        qL[k] = fma(q4, q1 - qm, q0);
+        qR[k] = fma(-q4, q2 - q0, q1);
+    }
+    FT Fn[NV3];
+    llf3n<FT>(A, qL, qR, F3_INTERIOR, Fn);
+    // Keep the gradient loads after the inviscid part (register pressure).
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int pn = dir == 0 ? 1 : S::PX;      // normal stride in a primitive plane
+    constexpr int pt = dir == 0 ? S::PX : 1;      // in-plane tangential stride
+    const int pb = (y + 1) * S::PX + x + 1;
+    const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+    FT g[3][3], uh[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const FT* U = P0 + c * S::PPL + pb;
+        const FT* Um = Pm + c * S::PPL + pb;
+        const FT* Up = Pp + c * S::PPL + pb;
+        uh[c] = h * (U[0] + U[pn]);
+        g[c][dir] = (U[pn] - U[0]) * inv_h[dir];
+        g[c][1 - dir] = ((U[pt] - U[-pt]) + (U[pn + pt] - U[pn - pt])) * (q4 * inv_h[1 - dir]);
+        g[c][2] = ((Up[0] - Um[0]) + (Up[pn] - Um[pn])) * (q4 * inv_h[2]);
+    }
+    const FT* Tt = P0 + 3 * S::PPL + pb;
+    const FT Tn = (Tt[pn] - Tt[0]) * inv_h[dir];
+    visc3n<FT, dir>(D, uh, g, Tn, Fn);
+    from_frame<FT, dir>(Fn, F);
+}
+
+// z-face above column cell (x, y) of plane z: the column's states at planes
+// z-1, z, z+1, z+2 (c0..c3, components rho, rho u, rho v, rho w, rho E) and
+// the primitive slots of planes z (Pa) and z+1 (Pb).
+template <class FT, class S>
+__device__ __forceinline__ void face_z(const StageArgs& A, const DomainArgs& D, const FT* c0, const FT* c1,
+                                       const FT* c2, const FT* c3, const FT* Pa, const FT* Pb, int x, int y,
+                                       int kind, FT F[NV3])
+{
+#pragma clang fp contract(off)
+    constexpr int comp[NV3] = {0, 3, 1, 2, 4};
+    const FT q4 = FT(0.25), h = FT(0.5);
+    FT qL[NV3], qR[NV3];
+#pragma unroll
+    for (int k = 0; k < NV3; ++k) {
+        const int v = comp[k];
+        qL[k] = fma(q4, c2[v] - c0[v], c1[v]);
+        qR[k] = fma(-q4, c3[v] - c1[v], c2[v]);
+    }
+    FT Fn[NV3];
+    llf3n<FT>(A, qL, qR, kind, Fn);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kind == F3_INTERIOR) {
+        FT g[3][3], uh[3];
+        const int pb = (y + 1) * S::PX + x + 1;
+        const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const FT* U = Pa + c * S::PPL + pb;
+            const FT* V = Pb + c * S::PPL + pb;
+            uh[c] = h * (U[0] + V[0]);
+            g[c][2] = (V[0] - U[0]) * inv_h[2];
+            g[c][0] = ((U[1] - U[-1]) + (V[1] - V[-1])) * (q4 * inv_h[0]);
+            g[c][1] = ((U[S::PX] - U[-S::PX]) + (V[S::PX] - V[-S::PX])) * (q4 * inv_h[1]);
+        }
+        const FT Tn = (Pb[3 * S::PPL + pb] - Pa[3 * S::PPL + pb]) * inv_h[2];
+        visc3n<FT, 2>(D, uh, g, Tn, Fn);
+    }
+    from_frame<FT, 2>(Fn, F);
+}
+
+template <int DOM, class FT, class S>
+__device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* smem)
+{
+    constexpr int TX = S::TX, TY = S::TY, LZ = S::LZ, NT = S::NT;
+    constexpr int HX = S::HX, QPL = S::QPL, PX = S::PX, PPL = S::PPL, NPOS = S::NPOS;
+    const DomainArgs& D = A.d[DOM];
+    const DomainArgs& O = A.d[1 - DOM];
+    const int tid = threadIdx.x;
+    const int nx = A.nx, ny = A.ny, nz = D.nz;
+    // Block -> (segment, x-y tile): the x-y tiles of one segment layer are
+    // consecutive (x fastest), so the workgroups that one XCD runs at a time
+    // are x-y neighbours and share their halo columns in its L2.
+    const int nxy = D.tiles_x * D.tiles_y;
+    const int seg = tile / nxy;
+    const int txy = tile - seg * nxy;
+    const int ty = txy / D.tiles_x, tx = txy - ty * D.tiles_x;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = (D.row_lo / LZ + seg) * LZ;
+    const int zs = max(z0, D.row_lo), ze = min(z0 + LZ, D.row_hi);
+    const int ncx = min(TX, nx - x0), ncy = min(TY, ny - y0);
+    const size_t rowsz = (size_t)ny * nx;
+
+    FT* Lq = (FT*)smem;                       // [2][5][HY][HX]
+    FT* Lp = Lq + S::LDS_Q;                   // [3][4][PY][PX]
+    FT* ex_x = Lp + S::LDS_P;                 // [5][TY][TX+1]
+    FT* ex_y = ex_x + NV3 * S::EXX;           // [5][TY+1][TX]
+    double* gf = (double*)(smem + (S::LDS_Q + S::LDS_P + S::LDS_X) * sizeof(FT));   // [3][TY*TX]
+
+    const int cx = tid % TX, cy = tid / TX;
+    const bool own = cx < ncx && cy < ncy;
+    const bool near = nx > TX && ny > TY;
+
+    // Staged positions of this thread (fixed for the segment).
+    size_t cofs[NPOS];
+    int ppos[NPOS];   // primitive index in a plane, or -1 outside the 1-cell ring
+#pragma unroll
+    for (int k = 0; k < NPOS; ++k) {
+        const int i = tid + k * NT;
+        const int yy = i / HX, xx = i - (i / HX) * HX;
+        const int col = near ? wrap1(x0 + xx - 2, nx) : wrapx(x0 + xx - 2, nx);
+        const int rowy = near ? wrap1(y0 + yy - 2, ny) : wrapx(y0 + yy - 2, ny);
+        cofs[k] = (size_t)rowy * nx + col;
+        ppos[k] = (i < QPL && xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= S::HY - 2)
+                      ? (yy - 1) * PX + xx - 1 : -1;
+    }
+
+    // Global loads of plane p (mirror planes beyond the domain, retained slow
+    // planes at substeps 2..m) into registers; returns the mirror flag.
+    auto load_plane = [&](int p, double (&val)[NPOS][NV3]) -> bool {
+        int pl = p;
+        bool neg = false;
+        if (pl < 0) { pl = 0; neg = true; }
+        else if (pl >= nz) { pl = nz - 1; neg = true; }
+        const double* src;
+        size_t vstride;
+        if (D.use_ret && (pl < D.b_lo || pl >= D.b_hi)) {
+            int rr = pl - D.ret_lo;
+            rr = rr < 0 ? 0 : (rr > 1 ? 1 : rr);
+            src = D.ret_in + (size_t)rr * rowsz;
+            vstride = 2 * rowsz;
+        } else {
+            src = D.qin + (size_t)pl * rowsz;
+            vstride = (size_t)nz * rowsz;
+        }
+#pragma unroll
+        for (int k = 0; k < NPOS; ++k)
+            if (tid + k * NT < QPL) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) val[k][v] = src[cofs[k] + v * vstride];
+            }
+        return neg;
+    };
+    // Plane p into its state slot (p & 1) and, from the same values, its
+    // primitives into primitive slot (p + 3) % 3.
+    auto commit_plane = [&](int p, const double (&val)[NPOS][NV3], bool neg) {
+        FT* Q = Lq + (p & 1) * NV3 * QPL;
+        FT* P = Lp + ((p + 3) % 3) * 4 * PPL;
+#pragma unroll
+        for (int k = 0; k < NPOS; ++k) {
+            const int i = tid + k * NT;
+            if (i < QPL) {
+                FT c[NV3];
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) {
+                    c[v] = FT((v == 3 && neg) ? -val[k][v] : val[k][v]);
+                    Q[v * QPL + i] = c[v];
+                }
+                if (ppos[k] >= 0) {
+                    FT pu, pv, pw, pT;
+                    prim3<FT>(c, FT(A.gamma), FT(A.gm1), pu, pv, pw, pT);
+                    P[ppos[k]] = pu;
+                    P[PPL + ppos[k]] = pv;
+                    P[2 * PPL + ppos[k]] = pw;
+                    P[3 * PPL + ppos[k]] = pT;
+                }
+            }
+        }
+    };
+    const int qown = (cy + 2) * HX + cx + 2;
+    auto read_col = [&](int p, FT (&c)[NV3]) {
+        const FT* Q = Lq + (p & 1) * NV3 * QPL;
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) c[v] = Q[v * QPL + qown];
+    };
+    auto pslot = [&](int p) -> const FT* { return Lp + ((p + 3) % 3) * 4 * PPL; };
+
+    __builtin_amdgcn_s_setprio(2);
+    // Interface flux per column (FP64 from the FP64 cells next to the lid),
+    // when the segment holds the row next to it.
+    const bool has_gamma = (DOM == 0) ? (D.gamma_top && ze == nz) : (D.gamma_bot && zs == 0);
+    if (has_gamma && tid < TX * TY) {
+        const int xx = tid % TX, yy = tid / TX;
+        const int col = near ? wrap1(x0 + xx, nx) : wrapx(x0 + xx, nx);
+        const int rowy = near ? wrap1(y0 + yy, ny) : wrapx(y0 + yy, ny);
+        const int ownp = (DOM == 0) ? nz - 1 : 0;
+        const int oth = (DOM == 0) ? 0 : O.nz - 1;
+        const size_t po = (size_t)nz * rowsz, pq = (size_t)O.nz * rowsz;
+        const double* a = D.qin + (size_t)ownp * rowsz + (size_t)rowy * nx + col;
+        const double* b = O.qin + (size_t)oth * rowsz + (size_t)rowy * nx + col;
+        double ca[NV3], cb[NV3];
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) { ca[v] = a[v * po]; cb[v] = b[v * pq]; }
+        double ua, va, Ta, ub, vb, Tb, f[3];
+        interface_cell3(ca, A.gamma, A.gm1, ua, va, Ta);
+        interface_cell3(cb, A.gamma, A.gm1, ub, vb, Tb);
+        if (DOM == 0) interface_flux3(A, ua, va, Ta, ub, vb, Tb, f);
+        else interface_flux3(A, ub, vb, Tb, ua, va, Ta, f);
+        gf[tid] = f[0];
+        gf[TX * TY + tid] = f[1];
+        gf[2 * TX * TY + tid] = f[2];
+    }
+
+    // ---- prologue: planes zs-2 .. zs+1, and the z-face below zs.
+    FT cm[NV3], c0[NV3], c1[NV3], c2[NV3];   // column: planes z-1, z (kept), z+1, z+2 (read per plane)
+    double va[NPOS][NV3];
+    {
+        bool na = load_plane(zs - 2, va);
+        commit_plane(zs - 2, va, na);
+        na = load_plane(zs - 1, va);
+        commit_plane(zs - 1, va, na);
+        __syncthreads();
+        FT cmm[NV3];
+        read_col(zs - 2, cmm);
+        read_col(zs - 1, cm);
+        __syncthreads();
+        na = load_plane(zs, va);
+        commit_plane(zs, va, na);
+        na = load_plane(zs + 1, va);
+        commit_plane(zs + 1, va, na);
+        __syncthreads();
+        read_col(zs, c0);
+        read_col(zs + 1, c1);
+        (void)cmm;
+        // the z-face below the first plane (bottom wall or lid when zs == 0)
+        FT Fb[NV3];
+        face_z<FT, S>(A, D, cmm, cm, c0, c1, pslot(zs - 1), pslot(zs), cx, cy,
+                      zs == 0 ? F3_BOTTOM : F3_INTERIOR, Fb);
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) c2[v] = Fb[v];   // c2 holds the lower face until the loop
+    }
+    FT Fbot[NV3];
+#pragma unroll
+    for (int v = 0; v < NV3; ++v) Fbot[v] = c2[v];
+    __builtin_amdgcn_s_setprio(0);
+
+    const double inv_dx = A.inv_dx, inv_dy = A.inv_dy, inv_dz = D.inv_dz;
+    const int col = x0 + cx, rowy = y0 + cy;
+    const size_t plane = (size_t)nz * rowsz;
+    const size_t nbx = (size_t)(D.b_hi - D.b_lo) * rowsz;
+
+    for (int z = zs; z < ze; ++z) {
+        // Global loads of plane z+2 (staged after this plane's x-y faces).
+        __builtin_amdgcn_s_setprio(2);
+        const bool nload = load_plane(z + 2, va);
+        __builtin_amdgcn_s_setprio(0);
+
+        // ---- x and y faces of plane z (own +x, +y; edge faces x = -1 in
+        // wave 0, y = -1 in wave 1), each written to the exchange at once (the
+        // previous plane's exchange reads ended at the last barrier).
+        {
+            const FT* Q = Lq + (z & 1) * NV3 * QPL;
+            const FT* Pm = pslot(z - 1);
+            const FT* P0 = pslot(z);
+            const FT* Pp = pslot(z + 1);
+            FT F[NV3];
+            if (own) {
+                face_xy<FT, 0, S>(A, D, Q, Pm, P0, Pp, cx, cy, F);
+                FT* e = ex_x + cy * (TX + 1) + cx + 1;
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) e[v * S::EXX] = F[v];
+                face_xy<FT, 1, S>(A, D, Q, Pm, P0, Pp, cx, cy, F);
+                FT* f = ex_y + (cy + 1) * TX + cx;
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) f[v * S::EXY] = F[v];
+            }
+            if (tid < ncy) {
+                face_xy<FT, 0, S>(A, D, Q, Pm, P0, Pp, -1, tid, F);
+                FT* e = ex_x + tid * (TX + 1);
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) e[v * S::EXX] = F[v];
+            }
+            if (tid >= 64 && tid - 64 < ncx) {
+                face_xy<FT, 1, S>(A, D, Q, Pm, P0, Pp, tid - 64, -1, F);
+                FT* f = ex_y + (tid - 64);
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) f[v * S::EXY] = F[v];
+            }
+            __syncthreads();   // plane z's state slot and plane z-1's primitives are free
+        }
+        // Plane z+2 into the freed slots.
+        commit_plane(z + 2, va, nload);
+
+        // Pointwise FP64 reads for the combination of plane z (the stage
+        // value itself when the fluxes are FP32, and the substep base U).
+        const bool inb = (z >= D.b_lo && z < D.b_hi);
+        const Combine cb = pick_combine(D.buf, D.main, inb);
+        const size_t id = (size_t)z * rowsz + (size_t)rowy * nx + col;
+        double qc[NV3], Ub[NV3];
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) {
+            Ub[v] = 0.0;
+            qc[v] = sizeof(FT) == 8 ? (double)c0[v] : 0.0;
+        }
+        if (own && sizeof(FT) != 8) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) qc[v] = D.qin[v * plane + id];
+        }
+        if (own && cb.mode != MODE_RHS && cb.alpha != 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) Ub[v] = D.base[v * plane + id];
+        }
+        __syncthreads();
+
+        // ---- z-face above plane z, divergence, source, combination.
+        read_col(z + 1, c1);
+        read_col(z + 2, c2);
+        FT Ftop[NV3];
+        face_z<FT, S>(A, D, cm, c0, c1, c2, pslot(z), pslot(z + 1), cx, cy,
+                      z == nz - 1 ? F3_TOP : F3_INTERIOR, Ftop);
+        if (own) {
+            double R[NV3];
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) {
+                const FT* fx = ex_x + v * S::EXX + cy * (TX + 1) + cx;
+                const FT* fy = ex_y + v * S::EXY + cy * TX + cx;
+                R[v] = -((double)fx[1] - (double)fx[0]) * inv_dx -
+                       ((double)fy[TX] - (double)fy[0]) * inv_dy -
+                       ((double)Ftop[v] - (double)Fbot[v]) * inv_dz;
+            }
+            const int gc = cy * TX + cx;
+            if (DOM == 0 && D.gamma_top && z == nz - 1) {
+                R[1] += gf[gc] * inv_dz;
+                R[2] += gf[TX * TY + gc] * inv_dz;
+                R[4] += gf[2 * TX * TY + gc] * inv_dz;
+            }
+            if (DOM == 1 && D.gamma_bot && z == 0) {
+                R[1] -= gf[gc] * inv_dz;
+                R[2] -= gf[TX * TY + gc] * inv_dz;
+                R[4] -= gf[2 * TX * TY + gc] * inv_dz;
+            }
+            R[3] += qc[0] * A.gravity;
+            R[4] += qc[3] * A.gravity;
+            if (cb.mode == MODE_RHS) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], R[v]);
+            } else if (cb.alpha == 0.0) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], qc[v] + cb.bh * R[v]);
+            } else {
+                double inc[NV3];
+#pragma unroll
+                for (int v = 0; v < NV3; ++v) inc[v] = cb.beta * (qc[v] - Ub[v]) + cb.bh * R[v];
+                if (cb.mode == MODE_STAGE) {
+#pragma unroll
+                    for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.out[v * plane + id], Ub[v] + inc[v]);
+                } else {
+                    const size_t ia = (size_t)(z - D.b_lo) * rowsz + (size_t)rowy * nx + col;
+                    if (cb.mode == MODE_ACC_FIRST) {
+#pragma unroll
+                        for (int v = 0; v < NV3; ++v) st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], inc[v]);
+                    } else if (cb.mode == MODE_ACC_ADD) {
+#pragma unroll
+                        for (int v = 0; v < NV3; ++v)
+                            st_dev(A.dev_stores != 0, &D.acc[v * nbx + ia], D.acc[v * nbx + ia] + inc[v]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NV3; ++v)
+                            st_dev(A.dev_stores != 0, &D.out[v * plane + id],
+                                   Ub[v] + (D.acc[v * nbx + ia] + inc[v]) * A.inv_m);
+                    }
+                }
+            }
+            if (D.ret_out && z >= D.ret_lo && z < D.ret_lo + 2) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v)
+                    st_dev(A.dev_stores != 0,
+                           &D.ret_out[(size_t)(v * 2 + z - D.ret_lo) * rowsz + (size_t)rowy * nx + col], qc[v]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV3; ++v) {
+            Fbot[v] = Ftop[v];
+            cm[v] = c0[v];
+            c0[v] = c1[v];
+        }
+        __syncthreads();   // exchange reads done before the next plane's faces
+    }
+}
+
+template <class FT, class S>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(MPRK3_MARCH_WAVES))) void march_kernel3(const StageArgs A)
+{
+    __shared__ __align__(16) char smem[S::template lds_bytes<FT>()];
+    const int b = xcd_contiguous(blockIdx.x, A.nblocks);
+    const int n0 = A.d[A.first].ntiles;
+    const int dom = (b < n0) ? A.first : 1 - A.first;
+    const int t = (b < n0) ? b : b - n0;
+    if (dom == 0) march_tile3<0, FT, S>(A, t, smem);
+    else march_tile3<1, FT, S>(A, t, smem);
+}
+
 }  // namespace
 
 hipError_t launch_stage3(const StageArgs& a, hipStream_t s)
 {
     if (a.nblocks <= 0) return hipSuccess;
-    if (a.flux32) hipLaunchKernelGGL(stage_kernel3<float>, dim3(a.nblocks), dim3(T32::NT), 0, s, a);
+    if (a.flux32) hipLaunchKernelGGL((march_kernel3<float, M32>), dim3(a.nblocks), dim3(M32::NT), 0, s, a);
     else hipLaunchKernelGGL(stage_kernel3<double>, dim3(a.nblocks), dim3(T64::NT), 0, s, a);
     return hipGetLastError();
 }
 
 KernelRef stage3_kernel_ref(bool flux32)
 {
-    if (flux32) return KernelRef{(const void*)stage_kernel3<float>, T32::NT};
+    if (flux32) return KernelRef{(const void*)march_kernel3<float, M32>, M32::NT};
     return KernelRef{(const void*)stage_kernel3<double>, T64::NT};
 }
 
 TileDims3 tile3_dims(bool flux32)
 {
-    if (flux32) return {T32::TX, T32::TY, T32::TZ, T32::NT};
+    if (flux32) return {M32::TX, M32::TY, M32::LZ, M32::NT};
     return {T64::TX, T64::TY, T64::TZ, T64::NT};
 }
 
