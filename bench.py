@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--serving-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--ensemble-steps", type=int, default=None, help="default: the members' 500")
+    ap.add_argument("--ensemble-mode", choices=["graph", "launch", "persistent"], default=None,
+                    help="time only this execution mode of the ensemble (no tuner, single-rate or "
+                         "equal-error runs; for profiling)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the equal-error comparison")
     ap.add_argument("--eq-steps", type=int, default=100,
                     help="horizon of the equal-error comparison, in slow steps of the stable dt")
@@ -99,7 +102,8 @@ def time_at_error(errors, times, target):
 
 
 KERNEL_SOURCES = {"stage_kernel": ("mprk_kernels.hip", "mprk_internal.h", "mprk_device.h"),
-                  "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h", "mprk_device.h")}
+                  "stage_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h", "mprk_device.h"),
+                  "march_kernel3": ("mprk_kernels3d.hip", "mprk_internal.h", "mprk_device.h")}
 
 
 def code_text(path: str) -> bytes:
@@ -459,6 +463,18 @@ def main():
 
     print(json.dumps(out), flush=True)
 
+    # Release every HIP object the run created (events, device tensors, the
+    # caching allocator's blocks) while the runtime is fully up, rather than
+    # in interpreter finalisation (where a profiler's own exit handlers may
+    # already be tearing the runtime down).
+    del lat, ev0, ev1
+    del tl, tu, tl0, tu0
+    import gc
+
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
 
 def equal_error_leg(args, torch, dev, w, tile, exec_mode):
     """MPRK against single-rate RK on the same GPU at equal error (the paper's
@@ -562,6 +578,17 @@ def equal_error_leg(args, torch, dev, w, tile, exec_mode):
     return res
 
 
+def cs_of(ws):
+    """MPRK cell-stage updates of one slow step of every member."""
+    from paper_2202_11890_amd import costmodel
+
+    cs = 0
+    for w in ws:
+        nF, nB, nS = costmodel.partition_counts(w.nx, w.nz_lower, w.nz_upper, w.n_buffer)
+        cs += costmodel.mprk_cell_stages(nF, nB, nS, w.m, w.base)
+    return cs
+
+
 def ensemble_leg(args, torch, dev):
     """Batched uneven ensemble (FP32 face fluxes, FP64 state).  Tile shape from
     the autotuner; every member advanced together with adaptive steps (each
@@ -594,6 +621,21 @@ def ensemble_leg(args, torch, dev):
             bt.set_dt(i, d if scale is None else d / scale[i])
 
     reset_dts(batch)
+    if args.ensemble_mode is not None:
+        mode = {"graph": mprk.EXEC_GRAPH, "launch": mprk.EXEC_LAUNCH,
+                "persistent": mprk.EXEC_PERSISTENT}[args.ensemble_mode]
+        batch.set_tile(mprk.TILE_32X8)
+        batch.set_exec(mode)
+        batch.set_adaptive(cr, dn)
+        t0 = time.perf_counter()
+        rc, st = batch.run_status(K, check_every=CH)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        batch.close()
+        print("# ensemble, %s mode only: %d steps in %.3f s" % (args.ensemble_mode, K, el),
+              file=sys.stderr, flush=True)
+        return {"mode": args.ensemble_mode, "steps": K, "seconds": el, "status": rc,
+                "value": cs_of(ws) * K / el, "unit": "cell-stage updates/s"}
     tuner_ms, best = batch.tune(3)
     print("# ensemble tuner (ms per slow step): %s -> %s" % (
         ", ".join("%s %.3f" % (mprk.TILE_NAMES[k], v) for k, v in enumerate(tuner_ms)),
@@ -625,9 +667,8 @@ def ensemble_leg(args, torch, dev):
     hist = []
     t_graph, bad = timed(batch, mprk.EXEC_GRAPH, K, hist)
     final = [(a.cpu().numpy(), b.cpu().numpy()) for a, b in tens]
-    k_short = max(CH, K // 10 // CH * CH)
     t_launch, _ = timed(batch, mprk.EXEC_LAUNCH, K)
-    t_pers, _ = timed(batch, mprk.EXEC_PERSISTENT, k_short)
+    t_pers, _ = timed(batch, mprk.EXEC_PERSISTENT, K)
     batch.close()
     rate = cs * K / t_graph
     print("# ensemble: %d members, %d steps in %.3f s (graph), %.3e cell-stage/s" % (
@@ -677,7 +718,7 @@ def ensemble_leg(args, torch, dev):
         "tile": mprk.TILE_NAMES[best],
         "tuner_ms_per_step": {mprk.TILE_NAMES[k]: v for k, v in enumerate(tuner_ms)},
         "modes": {"graph": rate, "launch": cs * K / t_launch,
-                  "persistent": cs * k_short / t_pers, "steps_persistent": k_short},
+                  "persistent": cs * K / t_pers, "steps_persistent": K},
         "single_rate": {"seconds": t_sr, "value": cs_sr * K / t_sr,
                         "time_to_solution_speedup": t_sr / t_graph,
                         "max_rel_diff_mprk_vs_single_rate": diff},
@@ -770,9 +811,9 @@ def ensemble_equal_error(args, torch, ws, tens, restore, dts0, tile):
         "members_capped": int(sum(h == "capped" for h in hows)),
         "status_bad": bad,
     }
-    print("# ensemble equal error: single rate %.3f s, MPRK at equal error %.3f s (speedup %.3f); "
+    print("# equal error per member (%d members): single rate %.3f s, MPRK at equal error %.3f s (speedup %.3f); "
           "median refinement %.2f, median error ratio %.1f" % (
-              t_sr, t_mprk_eq, t_sr / t_mprk_eq, np.median(kstar), np.median(ratio)),
+              len(ws), t_sr, t_mprk_eq, t_sr / t_mprk_eq, np.median(kstar), np.median(ratio)),
           file=sys.stderr, flush=True)
     return out
 
@@ -812,15 +853,17 @@ def leg_3d(args, torch, dev):
     per_launch = bytes_step / (w.m * w.base)
     avg = k_ms * 1e-3 / k_n
     gbs = per_launch / avg / 1e9
-    # the counter summary covers the FP32-flux kernel only
-    traffic = traffic_from_profiles("large3d", "stage_kernel3") if args.flux_3d == 32 else None
+    # FP32 fluxes run the z-marching kernel, FP64 fluxes the brick kernel; the
+    # counter summary covers the FP32-flux kernel only
+    kname = "march_kernel3" if args.flux_3d == 32 else "stage_kernel3"
+    traffic = traffic_from_profiles("large3d", kname) if args.flux_3d == 32 else None
     print("# 3d: %d steps, %.3f ms/step, %.3e cell-stage/s, stage kernel %.1f us, %.0f GB/s" % (
         K, 1e3 * t / K, cs * K / t, avg * 1e6, gbs), file=sys.stderr, flush=True)
     return {
         "workload": w.name + ", FP%d flux / FP64 state, dz_fast = dz_slow/4" % args.flux_3d,
         "value": cs * K / t, "unit": "cell-stage updates/s", "steps": K, "ms_per_step": 1e3 * t / K,
         "dt": dt, "status": st["status"], "cell_stages_per_step": cs,
-        "stage_kernel": {"avg_launch_us_bracketed": avg * 1e6,
+        "stage_kernel": {"kernel": kname, "avg_launch_us_bracketed": avg * 1e6,
                          "algorithmic_bytes_per_launch": int(per_launch),
                          "achieved_gbs": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
                          "traffic": traffic,
@@ -873,10 +916,30 @@ def serving_leg(args, torch, dev):
     print("# serving saturated: %d rebuilds, seconds %s" % (
         sat["batch_rebuilds"], {k: round(v, 3) for k, v in sat["host_seconds"].items()}),
         file=sys.stderr, flush=True)
+    eq = None
+    if not args.no_accuracy:
+        # Equal error per request, on the first 16 requests of the saturated
+        # set (the same study as the ensemble's).
+        sample = [w for _, w in inputs.serving_requests(16, 1.0, 11)]
+        tens = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+                for a, b in (inputs.initial_state(w) for w in sample)]
+        keep = [(a.clone(), b.clone()) for a, b in tens]
+
+        def restore():
+            for (a, b), (c, d) in zip(tens, keep):
+                a.copy_(c)
+                b.copy_(d)
+            torch.cuda.synchronize()
+
+        probe = mprk.Batch([(mprk.config_of_workload(w), a, b, 1.0) for w, (a, b) in zip(sample, tens)])
+        dts0 = probe.stable_dts(0.5, 0.25)
+        probe.close()
+        eq = ensemble_equal_error(args, torch, sample, tens, restore, dts0, None)
     return {
         "workload": "%d requests, nx log-uniform 64..1024 (nz = nx/2), 50..500 slow steps, m in {2,4}, "
                     "MPRK2, FP64; budget %d GiB, 64 slots, 10-step chunks" % (n, budget >> 30),
         "saturated": sat, "capacity_requests_per_s": capacity, "poisson": load,
+        "equal_error": eq,
     }
 
 

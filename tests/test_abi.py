@@ -261,7 +261,7 @@ def test_counter_profiles_are_reported_only_for_the_kernels_they_measured():
 
     import bench
 
-    for kernel, workload in (("stage_kernel", "large"), ("stage_kernel3", "large3d")):
+    for kernel, workload in (("stage_kernel", "large"), ("march_kernel3", "large3d")):
         path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.json" % (kernel, workload))
         d = json.load(open(path))
         assert d["hbm_bytes_per_launch"] > 0 and len(d["kernel_source_hash"]) >= 16
