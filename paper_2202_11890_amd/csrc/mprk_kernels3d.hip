@@ -600,7 +600,10 @@ __global__ __launch_bounds__(TileOf<FT>::S::NT) void stage_kernel3(const StageAr
 // previous plane (only a segment's first plane computes its lower face).  A
 // plane is staged once per segment (the brick kernel staged each cell of a
 // 2-plane z-halo for every 4-plane tile), and the next plane's global loads
-// are in flight while the current one is computed.
+// are in flight while the current one is computed.  A thread stages its own
+// cell itself and keeps the low word of its FP64 value, so that the FP64
+// stage value of the combination is rebuilt from the FP32 copy in LDS rather
+// than read from memory a second time.
 template <int X, int Y, int L>
 struct MShape {
     static constexpr int TX = X, TY = Y, LZ = L, NT = X * Y;
@@ -629,6 +632,35 @@ struct MShape {
 #define MPRK3_MARCH_WAVES 3
 #endif
 using M32 = MShape<MPRK3_MARCH_TX, MPRK3_MARCH_TY, MPRK3_MARCH_LZ>;
+
+// Low word of an FP64 value x whose FP32 copy (round to nearest) is hi.  When
+// hi is zero but x is not, the word is 1, which no zero has, so that
+// join_low declines it.
+__device__ __forceinline__ uint32_t low_word(double x, float hi)
+{
+    const uint32_t w = (uint32_t)(unsigned long long)__double_as_longlong(x);
+    return (hi == 0.0f && x != 0.0) ? 1u : w;
+}
+
+// The FP64 value from its FP32 round-to-nearest copy hi and its low word lo.
+// The value truncated to FP32 carries the FP64 value's sign, exponent and top
+// 20 significand bits, i.e. its high word.  That truncation is hi itself when
+// rounding went toward zero and hi one unit toward zero otherwise; the two
+// cases differ in the truncation's last significand bit, which is bit 29 of
+// lo, so comparing it with hi's last bit tells them apart.  Exact when the
+// truncation is a normal FP32 number, and for signed zeros; ok is false
+// otherwise (subnormal, tiny, overflowing and non-finite values), and the
+// caller reads the value from memory.
+__device__ __forceinline__ double join_low(float hi, uint32_t lo, bool& ok)
+{
+    const uint32_t hb = __float_as_uint(hi);
+    const uint32_t tb = hb - (((lo >> 29) ^ hb) & 1u);
+    const uint32_t hm = hb & 0x7fffffffu, tm = tb & 0x7fffffffu;
+    ok = (tm >= 0x00800000u && hm < 0x7f800000u) || (hm == 0u && lo == 0u);
+    const unsigned long long hw =
+        (unsigned long long)__double_as_longlong((double)__uint_as_float(tb)) & 0xffffffff00000000ull;
+    return __longlong_as_double((long long)(hw | lo));
+}
 
 // Inviscid LLF flux of a face in its normal frame from the reconstructed
 // states qL, qR (face frame: rho, normal, tangential 1, tangential 2,
@@ -829,19 +861,40 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
     const bool own = cx < ncx && cy < ncy;
     const bool near = nx > TX && ny > TY;
 
-    // Staged positions of this thread (fixed for the segment).
-    size_t cofs[NPOS];
+    // Staged positions of this thread (fixed for the segment): first its own
+    // cell, then, for the first QPL - NT threads, one cell of the 2-cell ring
+    // around the tile (the two rows below it, the two rows above it, then the
+    // two cells left and right of each row).
+    static_assert(NPOS == 2 && QPL - NT <= NT, "one own cell and at most one ring cell per thread");
+    constexpr int NRING = QPL - NT;
+    uint32_t cofs[NPOS];   // offset in a plane (a domain holds at most 2^28 cells)
+    int qpos[NPOS];   // index in a staged plane
     int ppos[NPOS];   // primitive index in a plane, or -1 outside the 1-cell ring
 #pragma unroll
     for (int k = 0; k < NPOS; ++k) {
-        const int i = tid + k * NT;
-        const int yy = i / HX, xx = i - (i / HX) * HX;
+        int xx, yy;
+        if (k == 0) {
+            xx = cx + 2;
+            yy = cy + 2;
+        } else if (tid < 2 * HX) {
+            yy = tid / HX;
+            xx = tid - yy * HX;
+        } else if (tid < 4 * HX) {
+            const int r = tid - 2 * HX;
+            yy = S::HY - 2 + r / HX;
+            xx = r - (r / HX) * HX;
+        } else {
+            const int s = min(tid, NRING - 1) - 4 * HX, j = s & 3;
+            yy = 2 + (s >> 2);
+            xx = j < 2 ? j : HX - 4 + j;
+        }
         const int col = near ? wrap1(x0 + xx - 2, nx) : wrapx(x0 + xx - 2, nx);
         const int rowy = near ? wrap1(y0 + yy - 2, ny) : wrapx(y0 + yy - 2, ny);
-        cofs[k] = (size_t)rowy * nx + col;
-        ppos[k] = (i < QPL && xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= S::HY - 2)
-                      ? (yy - 1) * PX + xx - 1 : -1;
+        cofs[k] = (uint32_t)(rowy * nx + col);
+        qpos[k] = yy * HX + xx;
+        ppos[k] = (xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= S::HY - 2) ? (yy - 1) * PX + xx - 1 : -1;
     }
+    const bool ring = tid < NRING;
 
     // Global loads of plane p (mirror planes beyond the domain, retained slow
     // planes at substeps 2..m) into registers; returns the mirror flag.
@@ -863,26 +916,30 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
         }
 #pragma unroll
         for (int k = 0; k < NPOS; ++k)
-            if (tid + k * NT < QPL) {
+            if (k == 0 || ring) {
 #pragma unroll
-                for (int v = 0; v < NV3; ++v) val[k][v] = src[cofs[k] + v * vstride];
+                for (int v = 0; v < NV3; ++v) val[k][v] = src[(size_t)cofs[k] + v * vstride];
             }
         return neg;
     };
     // Plane p into its state slot (p & 1) and, from the same values, its
-    // primitives into primitive slot (p + 3) % 3.
-    auto commit_plane = [&](int p, const double (&val)[NPOS][NV3], bool neg) {
+    // primitives into primitive slot (p + 3) % 3; lo receives the low words of
+    // the own cell's FP64 values (FP32 staging).
+    auto commit_plane = [&](int p, const double (&val)[NPOS][NV3], bool neg, uint32_t (&lo)[NV3]) {
         FT* Q = Lq + (p & 1) * NV3 * QPL;
         FT* P = Lp + ((p + 3) % 3) * 4 * PPL;
 #pragma unroll
         for (int k = 0; k < NPOS; ++k) {
-            const int i = tid + k * NT;
-            if (i < QPL) {
+            if (k == 0 || ring) {
                 FT c[NV3];
 #pragma unroll
                 for (int v = 0; v < NV3; ++v) {
-                    c[v] = FT((v == 3 && neg) ? -val[k][v] : val[k][v]);
-                    Q[v * QPL + i] = c[v];
+                    const double x = (v == 3 && neg) ? -val[k][v] : val[k][v];
+                    c[v] = FT(x);
+                    Q[v * QPL + qpos[k]] = c[v];
+                    if constexpr (sizeof(FT) == 4) {
+                        if (k == 0) lo[v] = low_word(x, c[v]);
+                    }
                 }
                 if (ppos[k] >= 0) {
                     FT pu, pv, pw, pT;
@@ -931,21 +988,22 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
 
     // ---- prologue: planes zs-2 .. zs+1, and the z-face below zs.
     FT cm[NV3], c0[NV3], c1[NV3], c2[NV3];   // column: planes z-1, z (kept), z+1, z+2 (read per plane)
+    uint32_t lo0[NV3], lo1[NV3], lo2[NV3];    // low words of the own cell at planes z, z+1, z+2
     double va[NPOS][NV3];
     {
         bool na = load_plane(zs - 2, va);
-        commit_plane(zs - 2, va, na);
+        commit_plane(zs - 2, va, na, lo0);
         na = load_plane(zs - 1, va);
-        commit_plane(zs - 1, va, na);
+        commit_plane(zs - 1, va, na, lo0);
         __syncthreads();
         FT cmm[NV3];
         read_col(zs - 2, cmm);
         read_col(zs - 1, cm);
         __syncthreads();
         na = load_plane(zs, va);
-        commit_plane(zs, va, na);
+        commit_plane(zs, va, na, lo0);
         na = load_plane(zs + 1, va);
-        commit_plane(zs + 1, va, na);
+        commit_plane(zs + 1, va, na, lo1);
         __syncthreads();
         read_col(zs, c0);
         read_col(zs + 1, c1);
@@ -1007,10 +1065,10 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
             __syncthreads();   // plane z's state slot and plane z-1's primitives are free
         }
         // Plane z+2 into the freed slots.
-        commit_plane(z + 2, va, nload);
+        commit_plane(z + 2, va, nload, lo2);
 
-        // Pointwise FP64 reads for the combination of plane z (the stage
-        // value itself when the fluxes are FP32, and the substep base U).
+        // The FP64 stage value of plane z (rebuilt from its FP32 copy and low
+        // word; read from memory where that declines) and the substep base U.
         const bool inb = (z >= D.b_lo && z < D.b_hi);
         const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)z * rowsz + (size_t)rowy * nx + col;
@@ -1018,11 +1076,13 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
 #pragma unroll
         for (int v = 0; v < NV3; ++v) {
             Ub[v] = 0.0;
-            qc[v] = sizeof(FT) == 8 ? (double)c0[v] : 0.0;
-        }
-        if (own && sizeof(FT) != 8) {
-#pragma unroll
-            for (int v = 0; v < NV3; ++v) qc[v] = D.qin[v * plane + id];
+            if constexpr (sizeof(FT) == 4) {
+                bool ok;
+                qc[v] = join_low(c0[v], lo0[v], ok);
+                if (own && !ok) qc[v] = D.qin[v * plane + id];
+            } else {
+                qc[v] = (double)c0[v];
+            }
         }
         if (own && cb.mode != MODE_RHS && cb.alpha != 0.0) {
 #pragma unroll
@@ -1101,6 +1161,8 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
             Fbot[v] = Ftop[v];
             cm[v] = c0[v];
             c0[v] = c1[v];
+            lo0[v] = lo1[v];
+            lo1[v] = lo2[v];
         }
         __syncthreads();   // exchange reads done before the next plane's faces
     }

@@ -1,0 +1,136 @@
+"""Stage values are combined in FP64 exactly when the face fluxes are FP32.
+
+A state whose FP32 copies are the same in every cell is a steady state of the
+discrete scheme with gravity off: every face of it sees the same FP32 inputs,
+so all face fluxes are equal, each divergence is exactly zero, the wall faces
+give the interior's pressure flux, and the interface flux of equal cells on
+both sides of the interface is zero.  Every stage value, buffer substep and
+accumulator of a slow step (eq. MRK2, Algorithm 1) then reproduces the FP64
+state.  The FP64 values below differ from cell to cell beneath FP32
+resolution, so the state comes back unchanged only if the stage combinations
+use each cell's own FP64 value, whatever copy of it the flux arithmetic used.
+The values cover FP32 rounding up and down, rounding up across a power of two,
+ties to even, signed zeros, values too small for FP32 and (in the 'tiny'
+case) values whose FP32 copy is subnormal.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2202_11890_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2202_11890_amd import mprk  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+# Offsets that keep the FP32 copy of the base value (round to nearest even).
+RHO = (1.0, [0.0, 2.0 ** -30, -(2.0 ** -30), 2.0 ** -24, -(2.0 ** -25), 2.0 ** -52, 3 * 2.0 ** -26])
+MX = (-0.375, [0.0, 2.0 ** -30, -(2.0 ** -30), 2.0 ** -26, -3 * 2.0 ** -28, 2.0 ** -50])
+MY = (0.5, [0.0, -(2.0 ** -40), -(2.0 ** -27), 2.0 ** -26, -(2.0 ** -26), 2.0 ** -30])
+EN = (2.5, [0.0, 2.0 ** -30, -(2.0 ** -31), 2.0 ** -24, -3 * 2.0 ** -25])
+# Values whose FP32 copy is a signed zero.
+TINY = [0.0, -0.0, 1e-300, -1e-300, 5e-324, 2.0 ** -150, -(2.0 ** -151), 1e-46, -3e-46]
+
+
+def fp32_uniform(a):
+    f = a.astype(np.float32)
+    return np.all(f == f.flat[0])
+
+
+def field(rng, shape, spec):
+    base, offs = spec
+    return base + rng.choice(np.array(offs), size=shape)
+
+
+def tiny(rng, shape):
+    return rng.choice(np.array(TINY), size=shape)
+
+
+def components(rng, shape, case):
+    """rho, the horizontal momenta, the vertical momentum, rho E."""
+    rho, en = field(rng, shape, RHO), field(rng, shape, EN)
+    if case == "rounding":
+        hor = [field(rng, shape, MX), field(rng, shape, MY)]
+    else:
+        hor = [tiny(rng, shape), np.full(shape, 1e-40)]
+    return rho, hor, tiny(rng, shape), en
+
+
+def state3(w, case, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for nz in (w.nz_lower, w.nz_upper):
+        rho, (mx, my), mz, en = components(rng, (nz, w.ny, w.nx), case)
+        out.append(np.stack([rho, mx, my, mz, en]))
+    ql, qu = out
+    # Equal FP64 cells on both sides of the interface: zero interface flux.
+    for v, c in enumerate([RHO[0], MX[0] if case == "rounding" else 0.0,
+                           MY[0] if case == "rounding" else 1e-40, 0.0, EN[0]]):
+        ql[v, -1] = c
+        qu[v, 0] = c
+    return ql, qu
+
+
+def state2(w, case, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for nz in (w.nz_lower, w.nz_upper):
+        rho, (mx, _), mz, en = components(rng, (nz, w.nx), case)
+        out.append(np.stack([rho, mx, mz, en]))
+    ql, qu = out
+    for v, c in enumerate([RHO[0], MX[0] if case == "rounding" else 0.0, 0.0, EN[0]]):
+        ql[v, -1] = c
+        qu[v, 0] = c
+    return ql, qu
+
+
+def check_unchanged(cfg, ql, qu, steps=2):
+    for q in (ql, qu):
+        for v in range(q.shape[0]):
+            assert fp32_uniform(q[v]), "test state is not FP32-uniform"
+    tl = torch.from_numpy(np.ascontiguousarray(ql)).to(DEV)
+    tu = torch.from_numpy(np.ascontiguousarray(qu)).to(DEV)
+    sol = mprk.Solver(cfg, tl, tu)
+    try:
+        st = sol.run(1e-3, steps)
+        torch.cuda.synchronize()
+        assert st["status"] == 0
+        gl, gu = tl.cpu().numpy(), tu.cpu().numpy()
+    finally:
+        sol.close()
+    for name, got, ref in (("lower", gl, ql), ("upper", gu, qu)):
+        bad = got != ref
+        assert not bad.any(), "%s: %d cells changed, first at %s: %r -> %r" % (
+            name, bad.sum(), np.argwhere(bad)[0], ref[tuple(np.argwhere(bad)[0])], got[tuple(np.argwhere(bad)[0])])
+
+
+GRIDS3 = [
+    # several tiles and z-segments of the marching kernel, ragged in x, y, z
+    dict(nx=70, ny=27, nz_lower=37, nz_upper=21),
+    # one tile narrower than the marching tile in x and y
+    dict(nx=24, ny=6, nz_lower=9, nz_upper=12),
+]
+
+
+@pytest.mark.parametrize("case", ["rounding", "tiny"])
+@pytest.mark.parametrize("grid", range(len(GRIDS3)))
+def test_fp32_uniform_state_is_kept_exactly_3d(case, grid):
+    w = inputs.small3d().with_(m=4, n_buffer=5, gravity=0.0, **GRIDS3[grid])
+    ql, qu = state3(w, case, seed=11 + grid)
+    print("3D", case, GRIDS3[grid], flush=True)
+    check_unchanged(mprk.config3_of_workload(w, flux_bits=32), ql, qu)
+
+
+@pytest.mark.parametrize("case", ["rounding", "tiny"])
+def test_fp32_uniform_state_is_kept_exactly_2d(case):
+    w = inputs.small().with_(nx=150, nz_lower=45, nz_upper=38, m=4, n_buffer=5)
+    ql, qu = state2(w, case, seed=5)
+    print("2D", case, flush=True)
+    check_unchanged(mprk.config_of_workload(w, flux_bits=32), ql, qu)
