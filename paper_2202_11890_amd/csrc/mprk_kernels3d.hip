@@ -923,9 +923,11 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
         return neg;
     };
     // Plane p into its state slot (p & 1) and, from the same values, its
-    // primitives into primitive slot (p + 3) % 3; lo receives the low words of
-    // the own cell's FP64 values (FP32 staging).
-    auto commit_plane = [&](int p, const double (&val)[NPOS][NV3], bool neg, uint32_t (&lo)[NV3]) {
+    // primitives into primitive slot (p + 3) % 3; mine receives the own
+    // cell's staged values and lo the low words of their FP64 values (FP32
+    // staging).
+    auto commit_plane = [&](int p, const double (&val)[NPOS][NV3], bool neg, FT (&mine)[NV3],
+                            uint32_t (&lo)[NV3]) {
         FT* Q = Lq + (p & 1) * NV3 * QPL;
         FT* P = Lp + ((p + 3) % 3) * 4 * PPL;
 #pragma unroll
@@ -937,6 +939,7 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
                     const double x = (v == 3 && neg) ? -val[k][v] : val[k][v];
                     c[v] = FT(x);
                     Q[v * QPL + qpos[k]] = c[v];
+                    if (k == 0) mine[v] = c[v];
                     if constexpr (sizeof(FT) == 4) {
                         if (k == 0) lo[v] = low_word(x, c[v]);
                     }
@@ -986,28 +989,23 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
         gf[2 * TX * TY + tid] = f[2];
     }
 
-    // ---- prologue: planes zs-2 .. zs+1, and the z-face below zs.
-    FT cm[NV3], c0[NV3], c1[NV3], c2[NV3];   // column: planes z-1, z (kept), z+1, z+2 (read per plane)
+    // ---- prologue: planes zs-2 .. zs+1, and the z-face below zs.  The own
+    // column comes from the thread's own staged cells; plane zs+1 overwrites
+    // the primitives of plane zs-2, which no face of this segment reads.
+    FT cm[NV3], c0[NV3], c1[NV3], c2[NV3];   // column: planes z-1, z (kept), z+1 (from LDS), z+2 (own commit)
     uint32_t lo0[NV3], lo1[NV3], lo2[NV3];    // low words of the own cell at planes z, z+1, z+2
     double va[NPOS][NV3];
     {
-        bool na = load_plane(zs - 2, va);
-        commit_plane(zs - 2, va, na, lo0);
-        na = load_plane(zs - 1, va);
-        commit_plane(zs - 1, va, na, lo0);
-        __syncthreads();
         FT cmm[NV3];
-        read_col(zs - 2, cmm);
-        read_col(zs - 1, cm);
-        __syncthreads();
+        bool na = load_plane(zs - 2, va);
+        commit_plane(zs - 2, va, na, cmm, lo0);
+        na = load_plane(zs - 1, va);
+        commit_plane(zs - 1, va, na, cm, lo0);
         na = load_plane(zs, va);
-        commit_plane(zs, va, na, lo0);
+        commit_plane(zs, va, na, c0, lo0);
         na = load_plane(zs + 1, va);
-        commit_plane(zs + 1, va, na, lo1);
+        commit_plane(zs + 1, va, na, c1, lo1);
         __syncthreads();
-        read_col(zs, c0);
-        read_col(zs + 1, c1);
-        (void)cmm;
         // the z-face below the first plane (bottom wall or lid when zs == 0)
         FT Fb[NV3];
         face_z<FT, S>(A, D, cmm, cm, c0, c1, pslot(zs - 1), pslot(zs), cx, cy,
@@ -1064,8 +1062,10 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
             }
             __syncthreads();   // plane z's state slot and plane z-1's primitives are free
         }
-        // Plane z+2 into the freed slots.
-        commit_plane(z + 2, va, nload, lo2);
+        // Plane z+2 into the freed slots.  What follows reads neither of them
+        // (the z-face takes plane z+2 from this thread's own commit), so the
+        // next barrier, at the end of the plane, also publishes this commit.
+        commit_plane(z + 2, va, nload, c2, lo2);
 
         // The FP64 stage value of plane z (rebuilt from its FP32 copy and low
         // word; read from memory where that declines) and the substep base U.
@@ -1088,11 +1088,9 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
 #pragma unroll
             for (int v = 0; v < NV3; ++v) Ub[v] = D.base[v * plane + id];
         }
-        __syncthreads();
 
         // ---- z-face above plane z, divergence, source, combination.
-        read_col(z + 1, c1);
-        read_col(z + 2, c2);
+        read_col(z + 1, c1);   // slot (z + 1) & 1, committed at the previous plane
         FT Ftop[NV3];
         face_z<FT, S>(A, D, cm, c0, c1, c2, pslot(z), pslot(z + 1), cx, cy,
                       z == nz - 1 ? F3_TOP : F3_INTERIOR, Ftop);
@@ -1164,7 +1162,7 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
             lo0[v] = lo1[v];
             lo1[v] = lo2[v];
         }
-        __syncthreads();   // exchange reads done before the next plane's faces
+        __syncthreads();   // exchange reads done and plane z+2 published before the next plane's faces
     }
 }
 
