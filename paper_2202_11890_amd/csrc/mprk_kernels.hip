@@ -41,13 +41,9 @@ struct Shape {
     static constexpr int LDS_Q = NV * HZ * HX;        // staged conserved state
     static constexpr int LDS_P = 3 * PZ * PX;         // staged primitives u, w, T
     static constexpr int LDS_EX = NV * Z * (X + 1) + NV * (Z + 1) * X;  // face fluxes
-    static constexpr int LOAD_RG = NT / HX;           // row groups of the loader
-    static constexpr int LOAD_THREADS = LOAD_RG * HX;
-    static constexpr int LOAD_ROWS = (HZ + LOAD_RG - 1) / LOAD_RG;  // rows per loader thread
     static_assert(Z % C == 0 && NT % 64 == 0 && NT <= 1024, "tile shape");
     static_assert(NT >= X + Z, "one edge face per thread of the first X + Z");
     static_assert(LDS_EX <= LDS_Q + LDS_P, "flux exchange must fit in the staged state");
-    static_assert(LOAD_RG >= 1, "loader needs a full row of threads");
     // Shared memory of one tile: the staged state and primitives in the flux
     // type FT (the flux exchange reuses that space), then the per-column
     // interface flux in FP64.
@@ -237,7 +233,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
 {
     MPRK_SHAPE_CONSTANTS(S);
     constexpr int LDS_Q = S::LDS_Q, LDS_P = S::LDS_P;
-    constexpr int LOAD_RG = S::LOAD_RG, LOAD_THREADS = S::LOAD_THREADS, LOAD_ROWS = S::LOAD_ROWS;
     const DomainArgs& D = A.d[DOM];
     const DomainArgs& O = A.d[1 - DOM];
     const int tid = threadIdx.x;
@@ -277,19 +272,43 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     __builtin_amdgcn_s_setprio(2);
 
     // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
-    // Each of LOAD_THREADS threads owns one tile column and LOAD_ROWS rows
-    // (stride LOAD_RG); all its global loads are issued before any is used.
-    if (tid < LOAD_THREADS) {
-        const int xc = tid % HX, rg = tid / HX;
-        const int col = nx > TX ? wrap1(x0 + xc - 2, nx) : wrapx(x0 + xc - 2, nx);
-        double val[LOAD_ROWS][NV];
-        bool neg[LOAD_ROWS];
+    // Each thread stages its own cell and, for the first NRING threads, one
+    // cell of the 2-cell ring around the tile (the two rows below it, the two
+    // rows above it, then the two cells left and right of each row); all its
+    // global loads are issued before any is used.  The own cell's FP64 values
+    // stay in registers as the stage value of the combination (FP32 staging).
+    static_assert(CZ == 1, "one cell per thread");
+    constexpr int NRING = HZ * HX - NT;
+    static_assert(NRING <= NT, "at most one ring cell per thread");
+    double qown[NV];
+    {
+        int xs[2], zs[2];
+        xs[0] = c + 2;
+        zs[0] = r0 + 2;
+        {
+            const int s = min(tid, NRING - 1);
+            if (s < 2 * HX) {
+                zs[1] = s / HX;
+                xs[1] = s - zs[1] * HX;
+            } else if (s < 4 * HX) {
+                const int q = s - 2 * HX;
+                zs[1] = HZ - 2 + q / HX;
+                xs[1] = q - (q / HX) * HX;
+            } else {
+                const int q = s - 4 * HX, j = q & 3;
+                zs[1] = 2 + (q >> 2);
+                xs[1] = j < 2 ? j : HX - 4 + j;
+            }
+        }
+        const bool ring = tid < NRING;
+        double val[2][NV];
+        bool neg[2];
 #pragma unroll
-        for (int k = 0; k < LOAD_ROWS; ++k) {
-            const int zr = rg + LOAD_RG * k;
+        for (int k = 0; k < 2; ++k) {
             neg[k] = false;
-            if (zr < HZ) {
-                int row = z0 + zr - 2;
+            if (k == 0 || ring) {
+                const int col = nx > TX ? wrap1(x0 + xs[k] - 2, nx) : wrapx(x0 + xs[k] - 2, nx);
+                int row = z0 + zs[k] - 2;
                 if (row < 0) { row = 0; neg[k] = true; }
                 else if (row >= nz) { row = nz - 1; neg[k] = true; }
                 const double* src;
@@ -308,9 +327,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
             }
         }
 #pragma unroll
-        for (int k = 0; k < LOAD_ROWS; ++k) {
-            const int zr = rg + LOAD_RG * k;
-            if (zr < HZ) {
+        for (int k = 0; k < 2; ++k) {
+            if (k == 0 || ring) {
+                const int zr = zs[k], xc = xs[k];
                 FT q[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -329,6 +348,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
                 }
             }
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qown[v] = val[0][v];
     }
     // Interface flux per column, FP64, from the FP64 cell averages of the two
     // cells next to the interface (the tiles on both sides compute the same
@@ -394,17 +415,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         const bool inb = (row >= D.b_lo && row < D.b_hi);
         const Combine cb = pick_combine(D.buf, D.main, inb);
         const size_t id = (size_t)row * nx + col;
+        // The stage value: the staged FP64 value itself (own rows that are
+        // computed are never mirror rows, nor taken from the retained rows).
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             Ub[h][v] = 0.0;
-            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx<S>(v, r0 + h, c)] : 0.0;
-        }
-        if (ok && sizeof(FT) != 8) {
-            // Stage values of this tile's own rows come from the state or the
-            // stage array (never from the retained rows: own rows are always
-            // computed rows, which are never taken from them).
-#pragma unroll
-            for (int v = 0; v < NV; ++v) qc[h][v] = D.qin[v * plane + id];
+            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx<S>(v, r0 + h, c)] : qown[v];
         }
         if (ok && cb.mode != MODE_RHS && cb.alpha != 0.0) {
 #pragma unroll
