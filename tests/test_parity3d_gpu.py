@@ -69,6 +69,8 @@ CASES = [
     ("fast-upper", inputs.small3d().with_(nx=18, ny=10, nz_lower=11, nz_upper=8, fast_is_lower=False,
                                           lz_lower=5.0, lz_upper=1.0, n_buffer=5)),
     ("viscous", inputs.small3d().with_(mu_lower=5e-3, mu_upper=2e-3, t_lower=2.0, gravity=-0.05)),
+    # several z-segments of the marching kernel (16 planes each), ragged in x, y and z
+    ("segments", inputs.small3d().with_(nx=40, ny=19, nz_lower=37, nz_upper=21, m=3, n_buffer=5)),
 ]
 
 
@@ -111,6 +113,7 @@ RUNS = [
     ("sr", inputs.small3d().with_(m=1), 6),
     ("ragged-m3", CASES[1][1], 6),
     ("fast-upper", CASES[2][1], 6),
+    ("segments-m3", CASES[4][1], 4),
 ]
 
 
