@@ -266,7 +266,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     for (int h = 0; h < CZ; ++h) okc[h] = (c < ncols) && (r0 + h >= vs) && (r0 + h < ve);
 
     // Waves raise their issue priority while they issue the tile's global
-    // loads (staging, and later the pointwise reads), so that the loads of
+    // loads (staging, and later the substep-base reads), so that the loads of
     // a workgroup leave early while the other workgroups of the CU compute
     // (2% per step on the 1024 x 512 workload).
     __builtin_amdgcn_s_setprio(2);
@@ -401,9 +401,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     if (ex_e) face_flux<FT, S>(A, D, L, e_z ? 1 : 0, e_c, e_r, kind_e, F[2 * CZ]);
 
     __builtin_amdgcn_s_setprio(2);
-    // Pointwise FP64 reads for the combination (the stage value itself when
-    // the fluxes are FP32, and the substep base U); they complete while the
-    // fluxes are exchanged.
+    // The stage value of the combination (staged FP64 registers, or the FP64
+    // tile) and the pointwise read of the substep base U, which completes
+    // while the fluxes are exchanged.
     const int col = x0 + c;
     const size_t plane = (size_t)nz * nx;
     const size_t nbx = (size_t)(D.b_hi - D.b_lo) * nx;
