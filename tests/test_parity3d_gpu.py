@@ -135,9 +135,16 @@ def test_run3_matches_oracle(name, w, n):
     assert np.all(el <= 1e-5) and np.all(eu <= 1e-5)
 
 
+CONS_GRIDS = [
+    dict(nx=16, ny=12, nz_lower=8, nz_upper=8),     # narrower than a tile in x: the edge face wraps in-tile
+    dict(nx=70, ny=27, nz_lower=20, nz_upper=18),   # several tiles and segments: edge faces shared by tiles
+]
+
+
+@pytest.mark.parametrize("grid", range(len(CONS_GRIDS)))
 @pytest.mark.parametrize("flux_bits", [64, 32])
-def test_conservation3_on_gpu(flux_bits):
-    w = inputs.small3d().with_(nx=16, ny=12, nz_lower=8, nz_upper=8, n_buffer=5)
+def test_conservation3_on_gpu(flux_bits, grid):
+    w = inputs.small3d().with_(n_buffer=5, **CONS_GRIDS[grid])
     ql, qu = inputs.random_state3(w, 3, amp=0.05)
     pb = prob3(w)
     dt = oracle.dt_rule3(pb, ql, qu, w.m)
