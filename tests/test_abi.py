@@ -63,6 +63,21 @@ def _cfg(**kw):
     ({"n_buffer": 3, "strict_buffer": 1}, mprk.OK),
     ({"n_buffer": 4, "base_rk": 3, "strict_buffer": 1}, mprk.EBUFFER),
     ({"n_buffer": 1, "m": 1, "strict_buffer": 1}, mprk.OK),
+    # empty and negative sizes
+    ({"nx": 0}, mprk.EINVAL),
+    ({"nx": -64}, mprk.EINVAL),
+    ({"nz_upper": 0}, mprk.EINVAL),
+    ({"dim": 3, "ny": 0, "dy": 0.1}, mprk.EINVAL),
+    # rate ratio 1..64
+    ({"m": 64}, mprk.OK),
+    ({"m": 65}, mprk.EINVAL),
+    # at most 2^28 cells per domain (no overflow in the product)
+    ({"nx": 1 << 18, "nz_lower": 1024, "nz_upper": 1024}, mprk.OK),
+    ({"nx": (1 << 18) + 1, "nz_lower": 1024, "nz_upper": 1024}, mprk.EINVAL),
+    ({"nx": (1 << 31) - 1}, mprk.EINVAL),
+    ({"dim": 3, "nx": 1024, "ny": 1024, "dy": 0.1, "nz_lower": 256, "nz_upper": 256}, mprk.OK),
+    ({"dim": 3, "nx": 1024, "ny": 1024, "dy": 0.1, "nz_lower": 256, "nz_upper": 257}, mprk.EINVAL),
+    ({"dim": 3, "nx": 1 << 16, "ny": 1 << 16, "dy": 0.1}, mprk.EINVAL),
 ])
 def test_validate(over, code):
     cfg = _cfg()

@@ -1,0 +1,147 @@
+"""Maximum sizes and empty runs through the C ABI.
+
+A domain may hold up to 2^28 cells.  At that size the oracle cannot follow the
+whole state, so the check uses a property that holds at any size: the scheme
+is translation invariant (periodic in x, and in y in 3D, with the same cell
+sizes), so a state made of P copies of a small periodic state stays P copies
+of the small problem's solution.  The test steps such a state at the size
+limit, checks that every copy is bit-for-bit the same (the tile width divides
+the period, so every copy sees the same tiles), and compares one copy with
+the oracle run on the small problem (1e-12 in FP64, the FP32 bound in 3D).
+The large contexts hold about 52 GB (2D) and 86 GB (3D) of device memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_11890_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2202_11890_amd import mprk  # noqa: E402
+from tests.test_oracle3d_pins import prob3  # noqa: E402
+from tests.test_parity3d_gpu import state_err3  # noqa: E402
+from tests.test_parity_gpu import problem_of, state_err  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MAX_CELLS = 1 << 28
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def copies_equal_first(t, reps, axis):
+    """Every one of `reps` equal blocks of t along `axis` equals the first."""
+    n = t.shape[axis] // reps
+    first = t.narrow(axis, 0, n)
+    for k in range(1, reps):
+        if not torch.equal(t.narrow(axis, k * n, n), first):
+            return k
+    return None
+
+
+def test_max_size_2d_periodic_copies_match_oracle():
+    period, nz = 64, 1024
+    nx = MAX_CELLS // nz                      # 262144 columns: exactly 2^28 cells per domain
+    reps = nx // period
+    small = inputs.small().with_(nx=period, nz_lower=nz, nz_upper=nz, m=2, base=2, n_buffer=4, seed=7)
+    big = small.with_(nx=nx, lx=small.lx * reps)
+    assert big.dx == small.dx and big.nx * big.nz_lower == MAX_CELLS
+    ql, qu = inputs.initial_state(small)
+    pb = problem_of(small)
+    dt = oracle.dt_rule(pb, ql, qu, small.m)
+    steps = 2
+    say("2D max size", big.nx, "x", nz, "x 2 domains,", reps, "copies of", period, "columns; dt", dt)
+    tl = dev(ql).repeat(1, 1, reps)
+    tu = dev(qu).repeat(1, 1, reps)
+    sol = mprk.Solver(mprk.config_of_workload(big), tl, tu)
+    try:
+        st = sol.run(dt, steps)
+        torch.cuda.synchronize()
+    finally:
+        sol.close()
+        del sol
+    assert st["status"] == 0
+    for name, t in (("lower", tl), ("upper", tu)):
+        bad = copies_equal_first(t, reps, 2)
+        assert bad is None, "%s: copy %d differs from copy 0" % (name, bad)
+    gl, gu = tl[:, :, :period].cpu().numpy(), tu[:, :, :period].cpu().numpy()
+    del tl, tu
+    torch.cuda.empty_cache()
+    ol, ou = ql.copy(), qu.copy()
+    oracle.mprk_run(pb, small.base, small.m, dt, steps, ol, ou)
+    el, eu = state_err(gl, ol), state_err(gu, ou)
+    say("  copy 0 vs oracle", el, eu)
+    assert np.all(el <= 1e-12) and np.all(eu <= 1e-12)
+
+
+def test_max_size_3d_periodic_copies_match_oracle():
+    px, py, nz = 32, 16, 256
+    nx, ny = 1024, 1024                       # 1024 x 1024 x 256 = 2^28 cells per domain
+    rx, ry = nx // px, ny // py
+    small = inputs.small3d().with_(nx=px, ny=py, nz_lower=nz, nz_upper=nz, m=2, n_buffer=5)
+    big = small.with_(nx=nx, ny=ny, lx=small.lx * rx, ly=small.ly * ry)
+    assert big.dx == small.dx and big.dy == small.dy and nx * ny * nz == MAX_CELLS
+    ql, qu = inputs.initial_state3(small)
+    pb = prob3(small)
+    dt = oracle.dt_rule3(pb, ql, qu, small.m)
+    steps = 2
+    say("3D max size", nx, "x", ny, "x", nz, "x 2 domains,", rx * ry, "copies; dt", dt)
+    tl = dev(ql).repeat(1, 1, ry, rx)
+    tu = dev(qu).repeat(1, 1, ry, rx)
+    sol = mprk.Solver(mprk.config3_of_workload(big, flux_bits=32), tl, tu)
+    try:
+        st = sol.run(dt, steps)
+        torch.cuda.synchronize()
+    finally:
+        sol.close()
+        del sol
+    assert st["status"] == 0
+    for name, t in (("lower", tl), ("upper", tu)):
+        rows = t.narrow(2, 0, py)
+        bad = copies_equal_first(rows, rx, 3)
+        assert bad is None, "%s: x copy %d differs from copy 0" % (name, bad)
+        bad = copies_equal_first(t, ry, 2)
+        assert bad is None, "%s: y copy %d differs from copy 0" % (name, bad)
+    gl = tl[:, :, :py, :px].cpu().numpy()
+    gu = tu[:, :, :py, :px].cpu().numpy()
+    del tl, tu
+    torch.cuda.empty_cache()
+    ol, ou = ql.copy(), qu.copy()
+    oracle.mprk_run3(pb, small.base, small.m, dt, steps, ol, ou)
+    el, eu = state_err3(gl, ol), state_err3(gu, ou)
+    say("  copy 0 vs oracle (FP32 fluxes)", el, eu)
+    assert np.all(el <= 1e-5) and np.all(eu <= 1e-5)
+
+
+def test_zero_steps_leave_the_state_alone_and_report_it():
+    w = inputs.small()
+    ql, qu = inputs.initial_state(w)
+    tl, tu = dev(ql), dev(qu)
+    sol = mprk.Solver(mprk.config_of_workload(w), tl, tu)
+    try:
+        d = sol.diagnostics()
+        st = sol.run(0.01, 0)
+        torch.cuda.synchronize()
+        assert st["status"] == 0 and st["steps_done"] == 0
+        assert st["totals_lower"] == d["totals_lower"] and st["totals_upper"] == d["totals_upper"]
+        assert np.array_equal(tl.cpu().numpy(), ql) and np.array_equal(tu.cpu().numpy(), qu)
+        rc, _ = mprk.mprk_run(sol.ctx, 0.01, -1, 0)
+        assert rc == mprk.EINVAL
+        for bad_dt in (0.0, -0.01, float("nan"), float("inf")):
+            rc, _ = mprk.mprk_run(sol.ctx, bad_dt, 1, 0)
+            assert rc == mprk.EINVAL
+        assert np.array_equal(tl.cpu().numpy(), ql) and np.array_equal(tu.cpu().numpy(), qu)
+    finally:
+        sol.close()
