@@ -325,20 +325,34 @@ def main():
         tl.copy_(tl0)
         tu.copy_(tu0)
         torch.cuda.synchronize()
+        e32a = torch.cuda.Event(enable_timing=True)
+        e32b = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e32a.record(f32.stream)
         fst = f32.run(dt, K, check_every=args.check_every)
+        e32b.record(f32.stream)
         torch.cuda.synchronize()
         t_32 = time.perf_counter() - t0
+        gpu32_ms = e32a.elapsed_time(e32b)
         f32.close()
+        del e32a, e32b
         dif = []
         for g, r in zip((tl.cpu().numpy(), tu.cpu().numpy()), mprk_final):
             scale = np.abs(r).max(axis=(1, 2))
             scale[1:3] = max(scale[1], scale[2])
             dif.append((np.abs(g - r).max(axis=(1, 2)) / scale).tolist())
+        # Same algorithmic bytes per stage launch as FP64 (the state, stage
+        # values and sums are FP64 either way); launch mode only.
+        launch32_s = gpu32_ms * 1e-3 / (K * launches_per_step)
+        ach32 = bytes_step / launches_per_step / launch32_s / 1e9
         out["fp32_flux"] = {
             "value": cs_step * K / t_32, "ms_per_step": 1e3 * t_32 / K, "status": fst["status"],
             "speedup_vs_f64": t_mprk / t_32, "tile": args.tile or "32x8",
             "max_rel_diff_vs_f64": {"lower": dif[0], "upper": dif[1]},
+            "roofline": None if args.exec != "launch" else {
+                "bound": "hbm", "kernel": "stage_kernel (FP32 fluxes)", "achieved": round(ach32, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach32 / HBM_PEAK_GBS, 4),
+                "avg_launch_us": round(launch32_s * 1e6, 3)},
         }
         print("# fp32 flux: %.1f us/step, speedup %.3f" % (1e6 * t_32 / K, t_mprk / t_32),
               file=sys.stderr, flush=True)

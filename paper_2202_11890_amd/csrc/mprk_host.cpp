@@ -203,6 +203,10 @@ StageArgs base_args(const Member& mb)
     a.inv_dx = 1.0 / g.dx;
     a.gamma = g.gamma;
     a.gm1 = g.gamma - 1.0;
+    a.inv_dx_f = (float)a.inv_dx;
+    a.inv_dy_f = (float)a.inv_dy;
+    a.gamma_f = (float)a.gamma;
+    a.gm1_f = (float)a.gm1;
     a.gravity = g.gravity;
     const double mu1 = g.mu_lower, mu2 = g.mu_upper;
     const double k1 = mu1 / ((g.gamma - 1.0) * g.prandtl);
@@ -220,6 +224,9 @@ StageArgs base_args(const Member& mb)
         D.inv_dz = 1.0 / D.dz;
         D.mu = d == 0 ? mu1 : mu2;
         D.kappa = d == 0 ? k1 : k2;
+        D.inv_dz_f = (float)D.inv_dz;
+        D.mu_f = (float)D.mu;
+        D.kappa_f = (float)D.kappa;
         D.gamma_top = d == 0;
         D.gamma_bot = d == 1;
         D.b_lo = D.b_hi = 0;

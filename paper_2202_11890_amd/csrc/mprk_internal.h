@@ -80,6 +80,7 @@ struct DomainArgs {
     int32_t tiles_y;         // 3D only (1 in 2D)
     double dz, inv_dz;
     double mu, kappa;
+    float inv_dz_f, mu_f, kappa_f, pad_f;   // FP32 copies (round to nearest) for FP32 fluxes
     Combine main;            // rows outside [b_lo, b_hi)
     Combine buf;             // rows inside  [b_lo, b_hi)
 };
@@ -95,6 +96,7 @@ struct StageArgs {
     int32_t dev_stores;      // 1: stage results stored with device coherence (see st_dev)
     double dx, inv_dx;
     double gamma, gm1, gravity;
+    float inv_dx_f, inv_dy_f, gamma_f, gm1_f;   // FP32 copies (round to nearest) for FP32 fluxes
     double bu, bT;           // bulk coefficients of the interface flux
     double half_dz1_mu1;     // dz_lower / (2 mu_lower): wall velocity u_w1 = u1 + sigma * this
     double inv_m;

@@ -137,7 +137,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     // obtain the same bits and the flux differences telescope exactly.
 #pragma clang fp contract(off)
     MPRK_SHAPE_CONSTANTS(S);
-    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT gamma = arg_ft<FT>(A.gamma, A.gamma_f), gm1 = arg_ft<FT>(A.gm1, A.gm1_f);
     const FT h = FT(0.5), q4 = FT(0.25);
     const int sn = dir ? HX : 1;             // normal stride in the state tile
     const int vn = dir ? 2 : 1;              // normal momentum component
@@ -211,20 +211,20 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
         const FT* Un = L.p + fn * pp + pb;
         const FT* Ut = L.p + ft * pp + pb;
         const FT* Tt = L.p + 2 * pp + pb;
-        const FT inv_n = FT(dir ? D.inv_dz : A.inv_dx);
-        const FT inv_t4 = FT(0.25 * (dir ? A.inv_dx : D.inv_dz));
+        const FT inv_n = (dir ? arg_ft<FT>(D.inv_dz, D.inv_dz_f) : arg_ft<FT>(A.inv_dx, A.inv_dx_f));
+        const FT inv_t4 = q4 * (dir ? arg_ft<FT>(A.inv_dx, A.inv_dx_f) : arg_ft<FT>(D.inv_dz, D.inv_dz_f));
         const FT unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
         const FT dn_un = (unB - unA) * inv_n;
         const FT dn_ut = (utB - utA) * inv_n;
         const FT dn_T = (Tt[pn] - Tt[0]) * inv_n;
         const FT dt_un = ((Un[pt] - Un[-pt]) + (Un[pn + pt] - Un[pn - pt])) * inv_t4;
         const FT dt_ut = ((Ut[pt] - Ut[-pt]) + (Ut[pn + pt] - Ut[pn - pt])) * inv_t4;
-        const FT mu = FT(D.mu);
+        const FT mu = arg_ft<FT>(D.mu, D.mu_f);
         const FT snn = mu * fma(FT(4.0 / 3.0), dn_un, FT(-2.0 / 3.0) * dt_ut);
         const FT snt = mu * (dn_ut + dt_un);
         F[1] = F[1] - snn;
         F[2] = F[2] - snt;
-        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, FT(D.kappa) * dn_T));
+        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, arg_ft<FT>(D.kappa, D.kappa_f) * dn_T));
     }
 }
 
@@ -340,7 +340,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
                 // staged values (primitive cell (zr - 1, xc - 1)).
                 if (xc >= 1 && xc <= HX - 2 && zr >= 1 && zr <= HZ - 2) {
                     FT u, w, T;
-                    primitives<FT>(q[0], q[1], q[2], q[3], FT(A.gamma), FT(A.gm1), u, w, T);
+                    primitives<FT>(q[0], q[1], q[2], q[3], arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), u, w, T);
                     const int pi = (zr - 1) * PX + xc - 1;
                     L.p[pi] = u;
                     L.p[PZ * PX + pi] = w;

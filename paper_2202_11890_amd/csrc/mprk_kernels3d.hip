@@ -128,7 +128,7 @@ __device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, c
                                       int y, int z, int kind, FT F[NV3])
 {
 #pragma clang fp contract(off)
-    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT gamma = arg_ft<FT>(A.gamma, A.gamma_f), gm1 = arg_ft<FT>(A.gm1, A.gm1_f);
     const FT h = FT(0.5), q4 = FT(0.25);
     constexpr int sn = dir == 0 ? 1 : (dir == 1 ? S::HX : S::QPL);
     constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;   // tangential directions
@@ -189,7 +189,7 @@ __device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, c
         constexpr int ps[3] = {1, S::PX, S::PPL};
         constexpr int pp = S::PZ * S::PPL;
         const int pb = p3<S>(0, z, y, x);
-        const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
         // g[c][d]: d u_c / d x_d at the face, c, d in (x, y, z)
         FT g[3][3], uh[3];
 #pragma unroll
@@ -208,13 +208,13 @@ __device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, c
         }
         const FT* Tt = L.p + 3 * pp + pb;
         const FT Tn = (Tt[pn] - Tt[0]) * inv_h[dir];
-        const FT mu = FT(D.mu);
+        const FT mu = arg_ft<FT>(D.mu, D.mu_f);
         FT sg[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             sg[c] = (c == dir) ? mu * fma(FT(4.0 / 3.0), g[dir][dir], FT(-2.0 / 3.0) * (g[t1][t1] + g[t2][t2]))
                                : mu * (g[dir][c] + g[c][dir]);
-        const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], FT(D.kappa) * Tn)));
+        const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], arg_ft<FT>(D.kappa, D.kappa_f) * Tn)));
         Fn[1] = Fn[1] - sg[dir];
         Fn[2] = Fn[2] - sg[t1];
         Fn[3] = Fn[3] - sg[t2];
@@ -361,7 +361,7 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
                     // same staged values (primitive cell (zz-1, yy-1, xx-1)).
                     if (xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= HY - 2 && zz >= 1 && zz <= HZ - 2) {
                         FT pu, pv, pw, pT;
-                        prim3<FT>(c, FT(A.gamma), FT(A.gm1), pu, pv, pw, pT);
+                        prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw, pT);
                         const int pi = ((zz - 1) * PY + yy - 1) * PX + xx - 1;
                         L.p[pi] = pu;
                         L.p[NPC + pi] = pv;
@@ -670,7 +670,7 @@ template <class FT>
 __device__ __forceinline__ void llf3n(const StageArgs& A, FT qL[NV3], FT qR[NV3], int kind, FT Fn[NV3])
 {
 #pragma clang fp contract(off)
-    const FT gamma = FT(A.gamma), gm1 = FT(A.gm1);
+    const FT gamma = arg_ft<FT>(A.gamma, A.gamma_f), gm1 = arg_ft<FT>(A.gm1, A.gm1_f);
     const FT h = FT(0.5);
     if (kind == F3_TOP) {
         qR[0] = qL[0]; qR[1] = -qL[1]; qR[2] = qL[2]; qR[3] = qL[3]; qR[4] = qL[4];
@@ -718,13 +718,13 @@ __device__ __forceinline__ void visc3n(const DomainArgs& D, const FT uh[3], cons
 {
 #pragma clang fp contract(off)
     constexpr int t1 = (dir + 1) % 3, t2 = (dir + 2) % 3;
-    const FT mu = FT(D.mu);
+    const FT mu = arg_ft<FT>(D.mu, D.mu_f);
     FT sg[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         sg[c] = (c == dir) ? mu * fma(FT(4.0 / 3.0), g[dir][dir], FT(-2.0 / 3.0) * (g[t1][t1] + g[t2][t2]))
                            : mu * (g[dir][c] + g[c][dir]);
-    const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], FT(D.kappa) * Tn)));
+    const FT en = fma(uh[0], sg[0], fma(uh[1], sg[1], fma(uh[2], sg[2], arg_ft<FT>(D.kappa, D.kappa_f) * Tn)));
     Fn[1] = Fn[1] - sg[dir];
     Fn[2] = Fn[2] - sg[t1];
     Fn[3] = Fn[3] - sg[t2];
@@ -771,7 +771,7 @@ __device__ __forceinline__ void face_xy(const StageArgs& A, const DomainArgs& D,
     constexpr int pn = dir == 0 ? 1 : S::PX;      // normal stride in a primitive plane
     constexpr int pt = dir == 0 ? S::PX : 1;      // in-plane tangential stride
     const int pb = (y + 1) * S::PX + x + 1;
-    const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+    const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
     FT g[3][3], uh[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -813,7 +813,7 @@ __device__ __forceinline__ void face_z(const StageArgs& A, const DomainArgs& D, 
     if (kind == F3_INTERIOR) {
         FT g[3][3], uh[3];
         const int pb = (y + 1) * S::PX + x + 1;
-        const FT inv_h[3] = {FT(A.inv_dx), FT(A.inv_dy), FT(D.inv_dz)};
+        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const FT* U = Pa + c * S::PPL + pb;
@@ -956,7 +956,7 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
                 }
                 if (ppos[k] >= 0) {
                     FT pu, pv, pw, pT;
-                    prim3<FT>(c, FT(A.gamma), FT(A.gm1), pu, pv, pw, pT);
+                    prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw, pT);
                     P[ppos[k]] = pu;
                     P[PPL + ppos[k]] = pv;
                     P[2 * PPL + ppos[k]] = pw;
