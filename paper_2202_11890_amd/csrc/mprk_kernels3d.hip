@@ -647,16 +647,17 @@ __device__ __forceinline__ uint32_t low_word(double x, float hi)
 // 20 significand bits, i.e. its high word.  That truncation is hi itself when
 // rounding went toward zero and hi one unit toward zero otherwise; the two
 // cases differ in the truncation's last significand bit, which is bit 29 of
-// lo, so comparing it with hi's last bit tells them apart.  Exact when the
-// truncation is a normal FP32 number, and for signed zeros; ok is false
-// otherwise (subnormal, tiny, overflowing and non-finite values), and the
-// caller reads the value from memory.
+// lo, so comparing it with hi's last bit tells them apart.  Exact when |hi|
+// lies strictly above the smallest normal FP32 number and below infinity (the
+// truncation is then a normal number), and for signed zeros; ok is false
+// otherwise (tiny, subnormal, overflowing and non-finite values, and |hi| equal
+// to the smallest normal), and the caller reads the value from memory.
 __device__ __forceinline__ double join_low(float hi, uint32_t lo, bool& ok)
 {
     const uint32_t hb = __float_as_uint(hi);
     const uint32_t tb = hb - (((lo >> 29) ^ hb) & 1u);
-    const uint32_t hm = hb & 0x7fffffffu, tm = tb & 0x7fffffffu;
-    ok = (tm >= 0x00800000u && hm < 0x7f800000u) || (hm == 0u && lo == 0u);
+    const uint32_t hm = hb & 0x7fffffffu;
+    ok = (hm - 0x00800001u < 0x7f800000u - 0x00800001u) || ((hm | lo) == 0u);
     const unsigned long long hw =
         (unsigned long long)__double_as_longlong((double)__uint_as_float(tb)) & 0xffffffff00000000ull;
     return __longlong_as_double((long long)(hw | lo));
@@ -1084,15 +1085,22 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
         const size_t id = (size_t)z * rowsz + (size_t)rowy * nx + col;
         double qc[NV3], Ub[NV3];
 #pragma unroll
-        for (int v = 0; v < NV3; ++v) {
-            Ub[v] = 0.0;
-            if constexpr (sizeof(FT) == 4) {
-                bool ok;
-                qc[v] = join_low(c0[v], lo0[v], ok);
-                if (own && !ok) qc[v] = D.qin[v * plane + id];
-            } else {
-                qc[v] = (double)c0[v];
+        for (int v = 0; v < NV3; ++v) Ub[v] = 0.0;
+        if constexpr (sizeof(FT) == 4) {
+            bool ok[NV3], all = true;
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) {
+                qc[v] = join_low(c0[v], lo0[v], ok[v]);
+                all = all && ok[v];
             }
+            if (own && !all) {
+#pragma unroll
+                for (int v = 0; v < NV3; ++v)
+                    if (!ok[v]) qc[v] = D.qin[v * plane + id];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV3; ++v) qc[v] = (double)c0[v];
         }
         if (own && cb.mode != MODE_RHS && cb.alpha != 0.0) {
 #pragma unroll
