@@ -262,3 +262,18 @@ def test_run3_full_size_matches_oracle():
     el, eu = state_err3(fl, ol), state_err3(fu, ou)
     say("run3 full size fp32 err", el, eu)
     assert np.all(el <= FP32_BOUND3) and np.all(eu <= FP32_BOUND3)
+
+
+def test_persistent_mode_is_refused_in_3d():
+    w = CASES[0][1]
+    ql, qu = inputs.initial_state3(w)
+    tl, tu = dev(ql), dev(qu)
+    sol = mprk.Solver(mprk.config3_of_workload(w, flux_bits=32), tl, tu)
+    try:
+        with pytest.raises(mprk.MprkError) as e:
+            sol.set_exec(mprk.EXEC_PERSISTENT)
+        assert e.value.code == mprk.EUNSUPPORTED
+        sol.set_exec(mprk.EXEC_GRAPH)          # the other modes stay available
+        sol.set_exec(mprk.EXEC_LAUNCH)
+    finally:
+        sol.close()
