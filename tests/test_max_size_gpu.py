@@ -41,6 +41,12 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+def need_free_bytes(n):
+    free, _ = torch.cuda.mem_get_info(DEV)
+    if free < n:
+        pytest.skip("needs %.0f GB of free device memory, %.0f GB free" % (n / 1e9, free / 1e9))
+
+
 def copies_equal_first(t, reps, axis):
     """Every one of `reps` equal blocks of t along `axis` equals the first."""
     n = t.shape[axis] // reps
@@ -62,10 +68,12 @@ def test_max_size_2d_periodic_copies_match_oracle():
     pb = problem_of(small)
     dt = oracle.dt_rule(pb, ql, qu, small.m)
     steps = 2
+    cfg = mprk.config_of_workload(big)
+    need_free_bytes(2 * 4 * MAX_CELLS * 8 + mprk.mprk_workspace_bytes(cfg) + (4 << 30))
     say("2D max size", big.nx, "x", nz, "x 2 domains,", reps, "copies of", period, "columns; dt", dt)
     tl = dev(ql).repeat(1, 1, reps)
     tu = dev(qu).repeat(1, 1, reps)
-    sol = mprk.Solver(mprk.config_of_workload(big), tl, tu)
+    sol = mprk.Solver(cfg, tl, tu)
     try:
         st = sol.run(dt, steps)
         torch.cuda.synchronize()
@@ -97,10 +105,12 @@ def test_max_size_3d_periodic_copies_match_oracle():
     pb = prob3(small)
     dt = oracle.dt_rule3(pb, ql, qu, small.m)
     steps = 2
+    cfg = mprk.config3_of_workload(big, flux_bits=32)
+    need_free_bytes(2 * 5 * MAX_CELLS * 8 + mprk.mprk_workspace_bytes(cfg) + (4 << 30))
     say("3D max size", nx, "x", ny, "x", nz, "x 2 domains,", rx * ry, "copies; dt", dt)
     tl = dev(ql).repeat(1, 1, ry, rx)
     tu = dev(qu).repeat(1, 1, ry, rx)
-    sol = mprk.Solver(mprk.config3_of_workload(big, flux_bits=32), tl, tu)
+    sol = mprk.Solver(cfg, tl, tu)
     try:
         st = sol.run(dt, steps)
         torch.cuda.synchronize()
