@@ -272,41 +272,50 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
     __builtin_amdgcn_s_setprio(2);
 
     // ---- stage the state tile (periodic in x, mirror rows beyond the domain).
-    // Each thread stages its own cell and, for the first NRING threads, one
-    // cell of the 2-cell ring around the tile (the two rows below it, the two
-    // rows above it, then the two cells left and right of each row); all its
-    // global loads are issued before any is used.  The own cell's FP64 values
-    // stay in registers as the stage value of the combination (FP32 staging).
-    static_assert(CZ == 1, "one cell per thread");
-    constexpr int NRING = HZ * HX - NT;
-    static_assert(NRING <= NT, "at most one ring cell per thread");
-    double qown[NV];
+    // Each thread stages its own CZ cells and, for the ring of 2 cells around
+    // the tile (the two rows below it, the two rows above it, then the two
+    // cells left and right of each row), ring cells tid, tid + NT, ...; all
+    // its global loads are issued before any is used.  The own cells' FP64
+    // values stay in registers as the stage values of the combination (FP32
+    // staging).
+    constexpr int NRING = HZ * HX - TX * TZ;
+    constexpr int NRP = (NRING + NT - 1) / NT;   // ring positions per thread
+    constexpr int NP = CZ + NRP;
+    double qown[CZ][NV];
     {
-        int xs[2], zs[2];
-        xs[0] = c + 2;
-        zs[0] = r0 + 2;
-        {
-            const int s = min(tid, NRING - 1);
-            if (s < 2 * HX) {
-                zs[1] = s / HX;
-                xs[1] = s - zs[1] * HX;
-            } else if (s < 4 * HX) {
-                const int q = s - 2 * HX;
-                zs[1] = HZ - 2 + q / HX;
-                xs[1] = q - (q / HX) * HX;
+        int xs[NP], zs[NP];
+        bool has[NP];
+#pragma unroll
+        for (int h = 0; h < CZ; ++h) {
+            xs[h] = c + 2;
+            zs[h] = r0 + h + 2;
+            has[h] = true;
+        }
+#pragma unroll
+        for (int j = 0; j < NRP; ++j) {
+            const int k = CZ + j;
+            const int s = tid + j * NT;
+            has[k] = s < NRING;
+            const int sc = min(s, NRING - 1);
+            if (sc < 2 * HX) {
+                zs[k] = sc / HX;
+                xs[k] = sc - zs[k] * HX;
+            } else if (sc < 4 * HX) {
+                const int q = sc - 2 * HX;
+                zs[k] = HZ - 2 + q / HX;
+                xs[k] = q - (q / HX) * HX;
             } else {
-                const int q = s - 4 * HX, j = q & 3;
-                zs[1] = 2 + (q >> 2);
-                xs[1] = j < 2 ? j : HX - 4 + j;
+                const int q = sc - 4 * HX, jj = q & 3;
+                zs[k] = 2 + (q >> 2);
+                xs[k] = jj < 2 ? jj : HX - 4 + jj;
             }
         }
-        const bool ring = tid < NRING;
-        double val[2][NV];
-        bool neg[2];
+        double val[NP][NV];
+        bool neg[NP];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NP; ++k) {
             neg[k] = false;
-            if (k == 0 || ring) {
+            if (has[k]) {
                 const int col = nx > TX ? wrap1(x0 + xs[k] - 2, nx) : wrapx(x0 + xs[k] - 2, nx);
                 int row = z0 + zs[k] - 2;
                 if (row < 0) { row = 0; neg[k] = true; }
@@ -327,8 +336,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
             }
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            if (k == 0 || ring) {
+        for (int k = 0; k < NP; ++k) {
+            if (has[k]) {
                 const int zr = zs[k], xc = xs[k];
                 FT q[NV];
 #pragma unroll
@@ -340,7 +349,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
                 // staged values (primitive cell (zr - 1, xc - 1)).
                 if (xc >= 1 && xc <= HX - 2 && zr >= 1 && zr <= HZ - 2) {
                     FT u, w, T;
-                    primitives<FT>(q[0], q[1], q[2], q[3], arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), u, w, T);
+                    primitives<FT>(q[0], q[1], q[2], q[3], arg_ft<FT>(A.gamma, A.gamma_f),
+                                   arg_ft<FT>(A.gm1, A.gm1_f), u, w, T);
                     const int pi = (zr - 1) * PX + xc - 1;
                     L.p[pi] = u;
                     L.p[PZ * PX + pi] = w;
@@ -349,7 +359,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
             }
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) qown[v] = val[0][v];
+        for (int h = 0; h < CZ; ++h)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qown[h][v] = val[h][v];
     }
     // Interface flux per column, FP64, from the FP64 cell averages of the two
     // cells next to the interface (the tiles on both sides compute the same
@@ -420,7 +432,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             Ub[h][v] = 0.0;
-            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx<S>(v, r0 + h, c)] : qown[v];
+            qc[h][v] = sizeof(FT) == 8 ? (double)L.q[qidx<S>(v, r0 + h, c)] : qown[h][v];
         }
         if (ok && cb.mode != MODE_RHS && cb.alpha != 0.0) {
 #pragma unroll
