@@ -189,7 +189,8 @@ __device__ __forceinline__ void face3(const StageArgs& A, const DomainArgs& D, c
         constexpr int ps[3] = {1, S::PX, S::PPL};
         constexpr int pp = S::PZ * S::PPL;
         const int pb = p3<S>(0, z, y, x);
-        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
+        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f),
+                             arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
         // g[c][d]: d u_c / d x_d at the face, c, d in (x, y, z)
         FT g[3][3], uh[3];
 #pragma unroll
@@ -361,7 +362,8 @@ __device__ __forceinline__ void stage_tile3(const StageArgs& A, int tile, char* 
                     // same staged values (primitive cell (zz-1, yy-1, xx-1)).
                     if (xx >= 1 && xx <= HX - 2 && yy >= 1 && yy <= HY - 2 && zz >= 1 && zz <= HZ - 2) {
                         FT pu, pv, pw, pT;
-                        prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw, pT);
+                        prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw,
+                              pT);
                         const int pi = ((zz - 1) * PY + yy - 1) * PX + xx - 1;
                         L.p[pi] = pu;
                         L.p[NPC + pi] = pv;
@@ -772,7 +774,8 @@ __device__ __forceinline__ void face_xy(const StageArgs& A, const DomainArgs& D,
     constexpr int pn = dir == 0 ? 1 : S::PX;      // normal stride in a primitive plane
     constexpr int pt = dir == 0 ? S::PX : 1;      // in-plane tangential stride
     const int pb = (y + 1) * S::PX + x + 1;
-    const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
+    const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f),
+                         arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
     FT g[3][3], uh[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -814,7 +817,8 @@ __device__ __forceinline__ void face_z(const StageArgs& A, const DomainArgs& D, 
     if (kind == F3_INTERIOR) {
         FT g[3][3], uh[3];
         const int pb = (y + 1) * S::PX + x + 1;
-        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f), arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
+        const FT inv_h[3] = {arg_ft<FT>(A.inv_dx, A.inv_dx_f), arg_ft<FT>(A.inv_dy, A.inv_dy_f),
+                             arg_ft<FT>(D.inv_dz, D.inv_dz_f)};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const FT* U = Pa + c * S::PPL + pb;
@@ -957,7 +961,8 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
                 }
                 if (ppos[k] >= 0) {
                     FT pu, pv, pw, pT;
-                    prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw, pT);
+                    prim3<FT>(c, arg_ft<FT>(A.gamma, A.gamma_f), arg_ft<FT>(A.gm1, A.gm1_f), pu, pv, pw,
+                              pT);
                     P[ppos[k]] = pu;
                     P[PPL + ppos[k]] = pv;
                     P[2 * PPL + ppos[k]] = pw;
@@ -1008,6 +1013,8 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
     double va[NPOS][NV3];
     {
         FT cmm[NV3];
+        // (planes zs-2 and zs-1 are never combined here: their low words go to
+        // lo0, which plane zs then overwrites)
         bool na = load_plane(zs - 2, va);
         commit_plane(zs - 2, va, na, cmm, lo0);
         na = load_plane(zs - 1, va);
@@ -1140,7 +1147,8 @@ __device__ __forceinline__ void march_tile3(const StageArgs& A, int tile, char* 
                 for (int v = 0; v < NV3; ++v) st_march(A.dev_stores != 0, &D.out[v * plane + id], R[v]);
             } else if (cb.alpha == 0.0) {
 #pragma unroll
-                for (int v = 0; v < NV3; ++v) st_march(A.dev_stores != 0, &D.out[v * plane + id], qc[v] + cb.bh * R[v]);
+                for (int v = 0; v < NV3; ++v)
+                    st_march(A.dev_stores != 0, &D.out[v * plane + id], qc[v] + cb.bh * R[v]);
             } else {
                 double inc[NV3];
 #pragma unroll
