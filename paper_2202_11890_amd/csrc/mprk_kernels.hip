@@ -211,8 +211,9 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
         const FT* Un = L.p + fn * pp + pb;
         const FT* Ut = L.p + ft * pp + pb;
         const FT* Tt = L.p + 2 * pp + pb;
-        const FT inv_n = (dir ? arg_ft<FT>(D.inv_dz, D.inv_dz_f) : arg_ft<FT>(A.inv_dx, A.inv_dx_f));
-        const FT inv_t4 = q4 * (dir ? arg_ft<FT>(A.inv_dx, A.inv_dx_f) : arg_ft<FT>(D.inv_dz, D.inv_dz_f));
+        const FT inv_x = arg_ft<FT>(A.inv_dx, A.inv_dx_f), inv_z = arg_ft<FT>(D.inv_dz, D.inv_dz_f);
+        const FT inv_n = dir ? inv_z : inv_x;
+        const FT inv_t4 = q4 * (dir ? inv_x : inv_z);
         const FT unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
         const FT dn_un = (unB - unA) * inv_n;
         const FT dn_ut = (utB - utA) * inv_n;
@@ -224,7 +225,8 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
         const FT snt = mu * (dn_ut + dt_un);
         F[1] = F[1] - snn;
         F[2] = F[2] - snt;
-        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, arg_ft<FT>(D.kappa, D.kappa_f) * dn_T));
+        const FT kappa = arg_ft<FT>(D.kappa, D.kappa_f);
+        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, kappa * dn_T));
     }
 }
 
