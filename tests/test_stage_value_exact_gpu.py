@@ -9,9 +9,10 @@ accumulator of a slow step (eq. MRK2, Algorithm 1) then reproduces the FP64
 state.  The FP64 values below differ from cell to cell beneath FP32
 resolution, so the state comes back unchanged only if the stage combinations
 use each cell's own FP64 value, whatever copy of it the flux arithmetic used.
-The values cover FP32 rounding up and down, rounding up across a power of two,
-ties to even, signed zeros, values too small for FP32 and (in the 'tiny'
-case) values whose FP32 copy is subnormal.
+The values cover FP32 rounding up and down, rounding up across a power of two
+(positive and negative), ties to even, signed zeros, values too small for
+FP32, values whose FP32 copy is subnormal ('tiny') and values whose FP32 copy
+is the smallest normal FP32 number ('edges').
 """
 from __future__ import annotations
 
@@ -37,6 +38,11 @@ MY = (0.5, [0.0, -(2.0 ** -40), -(2.0 ** -27), 2.0 ** -26, -(2.0 ** -26), 2.0 **
 EN = (2.5, [0.0, 2.0 ** -30, -(2.0 ** -31), 2.0 ** -24, -3 * 2.0 ** -25])
 # Values whose FP32 copy is a signed zero.
 TINY = [0.0, -0.0, 1e-300, -1e-300, 5e-324, 2.0 ** -150, -(2.0 ** -151), 1e-46, -3e-46]
+# Values whose FP32 copy is the smallest normal FP32 number (some of them below it), and negative
+# values rounding across a power of two.
+FMIN = float(np.finfo(np.float32).tiny)
+MX_EDGE = (FMIN, [0.0, FMIN * 2.0 ** -30, -FMIN * 2.0 ** -30, FMIN * 2.0 ** -26, -FMIN * 2.0 ** -25])
+MY_EDGE = (-0.5, [0.0, 2.0 ** -40, -(2.0 ** -30), 2.0 ** -27, -(2.0 ** -26)])
 
 
 def fp32_uniform(a):
@@ -58,6 +64,8 @@ def components(rng, shape, case):
     rho, en = field(rng, shape, RHO), field(rng, shape, EN)
     if case == "rounding":
         hor = [field(rng, shape, MX), field(rng, shape, MY)]
+    elif case == "edges":
+        hor = [field(rng, shape, MX_EDGE), field(rng, shape, MY_EDGE)]
     else:
         hor = [tiny(rng, shape), np.full(shape, 1e-40)]
     return rho, hor, tiny(rng, shape), en
@@ -71,8 +79,9 @@ def state3(w, case, seed):
         out.append(np.stack([rho, mx, my, mz, en]))
     ql, qu = out
     # Equal FP64 cells on both sides of the interface: zero interface flux.
-    for v, c in enumerate([RHO[0], MX[0] if case == "rounding" else 0.0,
-                           MY[0] if case == "rounding" else 1e-40, 0.0, EN[0]]):
+    base_mx = {"rounding": MX[0], "edges": MX_EDGE[0]}.get(case, 0.0)
+    base_my = {"rounding": MY[0], "edges": MY_EDGE[0]}.get(case, 1e-40)
+    for v, c in enumerate([RHO[0], base_mx, base_my, 0.0, EN[0]]):
         ql[v, -1] = c
         qu[v, 0] = c
     return ql, qu
@@ -85,7 +94,8 @@ def state2(w, case, seed):
         rho, (mx, _), mz, en = components(rng, (nz, w.nx), case)
         out.append(np.stack([rho, mx, mz, en]))
     ql, qu = out
-    for v, c in enumerate([RHO[0], MX[0] if case == "rounding" else 0.0, 0.0, EN[0]]):
+    base_mx = {"rounding": MX[0], "edges": MX_EDGE[0]}.get(case, 0.0)
+    for v, c in enumerate([RHO[0], base_mx, 0.0, EN[0]]):
         ql[v, -1] = c
         qu[v, 0] = c
     return ql, qu
@@ -119,7 +129,7 @@ GRIDS3 = [
 ]
 
 
-@pytest.mark.parametrize("case", ["rounding", "tiny"])
+@pytest.mark.parametrize("case", ["rounding", "tiny", "edges"])
 @pytest.mark.parametrize("grid", range(len(GRIDS3)))
 def test_fp32_uniform_state_is_kept_exactly_3d(case, grid):
     w = inputs.small3d().with_(m=4, n_buffer=5, gravity=0.0, **GRIDS3[grid])
@@ -128,7 +138,7 @@ def test_fp32_uniform_state_is_kept_exactly_3d(case, grid):
     check_unchanged(mprk.config3_of_workload(w, flux_bits=32), ql, qu)
 
 
-@pytest.mark.parametrize("case", ["rounding", "tiny"])
+@pytest.mark.parametrize("case", ["rounding", "tiny", "edges"])
 def test_fp32_uniform_state_is_kept_exactly_2d(case):
     w = inputs.small().with_(nx=150, nz_lower=45, nz_upper=38, m=4, n_buffer=5)
     ql, qu = state2(w, case, seed=5)
