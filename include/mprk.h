@@ -103,17 +103,18 @@ enum mprk_region {
 typedef struct mprk_config {
     int32_t abi_version;    /* must be MPRK_ABI_VERSION                              */
     int32_t dim;            /* 2 (x-z plane) or 3 (x-y-z)                            */
-    int32_t nx, ny;         /* cells in x and y (periodic); ny must be 1 when dim == 2,
-                               >= 4 when dim == 3                                     */
-    int32_t nz_lower;       /* rows of the lower domain                              */
-    int32_t nz_upper;       /* rows of the upper domain                              */
+    int32_t nx, ny;         /* cells in x and y (periodic); nx >= 4; ny must be 1 when
+                               dim == 2, >= 4 when dim == 3                           */
+    int32_t nz_lower;       /* rows of the lower domain (>= 3)                       */
+    int32_t nz_upper;       /* rows of the upper domain (>= 3); a domain holds at most
+                               2^28 cells (nx * ny * nz)                              */
     double dx, dy;          /* cell sizes in x (and y); dy is ignored in 2D          */
     double dz_lower;        /* cell height of the lower domain                       */
     double dz_upper;        /* cell height of the upper domain                       */
     int32_t fast_is_lower;  /* 1: the lower domain is F; 0: the upper domain is F    */
     int32_t n_buffer;       /* slow rows next to Gamma forming B, 1..nz_slow-2       */
     int32_t base_rk;        /* 2: two-stage RK2 of Table 1; 3: three-stage SSP-RK3   */
-    int32_t m;              /* rate ratio >= 1; m == 1 is the single-rate base method */
+    int32_t m;              /* rate ratio 1..64; m == 1 is the single-rate base method */
     double gamma;           /* ratio of specific heats (> 1)                         */
     double prandtl;         /* Prandtl number (> 0)                                  */
     double mu_lower;        /* nondimensional viscosity of the lower domain (> 0)    */
@@ -193,8 +194,10 @@ int mprk_step(mprk_ctx* ctx, double dt);
  * conserved when the buffer is long enough, Remark 1) and synchronises the
  * stream; returns
  * MPRK_ENONFINITE at the first check that sees a bad state.  check_every <= 0
- * checks only after the last step.  If out != NULL it receives the stats of
- * the last check. */
+ * checks only after the last step.  nsteps == 0 leaves the state alone and
+ * only runs the reductions; nsteps < 0, or nsteps > 0 with a dt that is not
+ * positive and finite, returns MPRK_EINVAL without touching the state.  If
+ * out != NULL it receives the stats of the last check. */
 int mprk_run(mprk_ctx* ctx, double dt, int64_t nsteps, int64_t check_every, mprk_stats* out);
 
 /* Device reductions on the context's current state (totals, stability
