@@ -57,6 +57,16 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(y, fma(-x, y, 1.0), y);
 }
 
+// A kernel argument in the flux type.  The launch record carries FP32 copies,
+// rounded to nearest on the host as FT(x) would round them, so FP32 kernels
+// take them as uniform operands instead of converting them at every face.
+template <class FT>
+__device__ __forceinline__ FT arg_ft(double d, float f)
+{
+    if constexpr (sizeof(FT) == 4) return f;
+    else return d;
+}
+
 // Reciprocal, square root and reciprocal square root of positive normal
 // arguments in the flux type.  FP64: hardware estimates refined by Newton
 // steps (a few ulp).  FP32: the hardware instructions (1 ulp).  No scaling
@@ -68,16 +78,6 @@ __device__ __forceinline__ double rcp_nr(double x)
 // does not enter the physical flux: in FP64 they take one Newton step from
 // the hardware estimate, whose relative error is then the square of the
 // estimate's (about 1e-14 and below).
-// A kernel argument in the flux type.  The launch record carries FP32 copies,
-// rounded to nearest on the host as FT(x) would round them, so FP32 kernels
-// take them as uniform operands instead of converting them at every face.
-template <class FT>
-__device__ __forceinline__ FT arg_ft(double d, float f)
-{
-    if constexpr (sizeof(FT) == 4) return f;
-    else return d;
-}
-
 template <class FT> struct Fm;
 template <> struct Fm<double> {
     static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }
