@@ -77,7 +77,8 @@ __device__ __forceinline__ FT arg_ft(double d, float f)
 // flux (sound speeds and Roe weights), which scales the dissipation term and
 // does not enter the physical flux: in FP64 they take one Newton step from
 // the hardware estimate, whose relative error is then the square of the
-// estimate's (about 1e-14 and below).
+// estimate's (about 1e-14 and below).  inv_sqrt gives a face state's 1/rho
+// for the physical flux and its sqrt(rho), 1/sqrt(rho) for the Roe weights.
 template <class FT> struct Fm;
 template <> struct Fm<double> {
     static __device__ __forceinline__ double rcp(double x) { return rcp_nr(x); }
@@ -95,6 +96,19 @@ template <> struct Fm<double> {
         const double y = __builtin_amdgcn_rcp(x);
         return fma(y, fma(-x, y, 1.0), y);
     }
+    // r = 1/x to about an ulp, and y = 1/sqrt(x), s = sqrt(x) to wave-speed
+    // accuracy, from one reciprocal square root: y is one Newton step from
+    // the estimate (relative error about 1e-14), s = x y, and y^2 is refined
+    // by one Newton step of the reciprocal, whose error is then the square
+    // of y^2's.
+    static __device__ __forceinline__ void inv_sqrt(double x, double& r, double& y, double& s)
+    {
+        const double y0 = __builtin_amdgcn_rsq(x);
+        y = fma(0.5 * y0, fma(-(x * y0), y0, 1.0), y0);
+        s = x * y;
+        const double r1 = y * y;
+        r = fma(r1, fma(-x, r1, 1.0), r1);
+    }
 };
 template <> struct Fm<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -102,7 +116,21 @@ template <> struct Fm<float> {
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float ws_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float ws_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ void inv_sqrt(float x, float& r, float& y, float& s)
+    {
+        y = __builtin_amdgcn_rsqf(x);
+        r = y * y;
+        s = x * y;
+    }
 };
+
+// Viscous coefficient `row` (VK_*) of direction d in the flux type.
+template <class FT>
+__device__ __forceinline__ FT arg_vk(const DomainArgs& D, int row, int d)
+{
+    if constexpr (sizeof(FT) == 4) return D.vk_f[row][d];
+    else return D.vk[row][d];
+}
 
 // The combination of a row: the buffer's or the main one.  Both records are
 // read as (uniform) kernel arguments and selected per lane, so that no lane

@@ -201,6 +201,8 @@ StageArgs base_args(const Member& mb)
     a.inv_dy = g.dim == 3 ? 1.0 / g.dy : 0.0;
     a.dx = g.dx;
     a.inv_dx = 1.0 / g.dx;
+    a.hinv_dx = 0.5 * a.inv_dx;
+    a.hinv_dy = 0.5 * a.inv_dy;
     a.gamma = g.gamma;
     a.gm1 = g.gamma - 1.0;
     a.inv_dx_f = (float)a.inv_dx;
@@ -222,11 +224,23 @@ StageArgs base_args(const Member& mb)
         D.nz = d == 0 ? g.nz_lower : g.nz_upper;
         D.dz = d == 0 ? dz1 : dz2;
         D.inv_dz = 1.0 / D.dz;
+        D.hinv_dz = 0.5 * D.inv_dz;
         D.mu = d == 0 ? mu1 : mu2;
         D.kappa = d == 0 ? k1 : k2;
         D.inv_dz_f = (float)D.inv_dz;
         D.mu_f = (float)D.mu;
         D.kappa_f = (float)D.kappa;
+        // Viscous coefficients per direction (x, y, z), folded so that a face
+        // scales raw differences of the staged primitives once.
+        const double inv_h[3] = {a.inv_dx, a.inv_dy, D.inv_dz};
+        for (int k = 0; k < 3; ++k) {
+            D.vk[VK_NN][k] = (4.0 / 3.0) * D.mu * inv_h[k];
+            D.vk[VK_N][k] = D.mu * inv_h[k];
+            D.vk[VK_Q][k] = 2.0 * D.kappa * inv_h[k];
+            D.vk[VK_TT][k] = (-2.0 / 3.0) * D.mu * (0.25 * inv_h[k]);
+            D.vk[VK_TN][k] = D.mu * (0.25 * inv_h[k]);
+            for (int r = 0; r < 5; ++r) D.vk_f[r][k] = (float)D.vk[r][k];
+        }
         D.gamma_top = d == 0;
         D.gamma_bot = d == 1;
         D.b_lo = D.b_hi = 0;

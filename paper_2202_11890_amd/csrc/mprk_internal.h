@@ -59,6 +59,9 @@ struct Combine {
     int32_t pad;
 };
 
+// Rows of DomainArgs::vk.
+enum : int { VK_NN = 0, VK_N = 1, VK_Q = 2, VK_TT = 3, VK_TN = 4 };
+
 // Domain arrays are [nv][nz][ny][nx] (ny = 1 in 2D); a "row" is a z-plane.
 struct DomainArgs {
     const double* qin;     // stage value read by the stencil [nv][nz][ny][nx]
@@ -79,8 +82,18 @@ struct DomainArgs {
     int32_t tiles_x, tiles_z, ntiles;
     int32_t tiles_y;         // 3D only (1 in 2D)
     double dz, inv_dz;
+    double hinv_dz;          // inv_dz / 2: the face routines return twice the flux
     double mu, kappa;
     float inv_dz_f, mu_f, kappa_f, pad_f;   // FP32 copies (round to nearest) for FP32 fluxes
+    // Viscous coefficients of the face routines, per direction d (0 x, 1 y,
+    // 2 z; 2D uses x and z), applied to raw differences of the staged
+    // primitives: [VK_NN] 4/3 mu / h_d and [VK_N] mu / h_d (normal
+    // derivatives), [VK_Q] 2 kappa / h_d (heat flux of the doubled flux),
+    // [VK_TT] -2/3 mu / (4 h_d) and [VK_TN] mu / (4 h_d) (tangential
+    // derivatives, averaged over the two cells of the face).
+    double vk[5][3];
+    float vk_f[5][3];
+    float pad_vk;
     Combine main;            // rows outside [b_lo, b_hi)
     Combine buf;             // rows inside  [b_lo, b_hi)
 };
@@ -95,6 +108,7 @@ struct StageArgs {
     int32_t flux32;          // 1: face fluxes in FP32 (state, stage sums, interface flux FP64)
     int32_t dev_stores;      // 1: stage results stored with device coherence (see st_dev)
     double dx, inv_dx;
+    double hinv_dx, hinv_dy;  // inv_dx / 2, inv_dy / 2 (divergence of the doubled fluxes)
     double gamma, gm1, gravity;
     float inv_dx_f, inv_dy_f, gamma_f, gm1_f;   // FP32 copies (round to nearest) for FP32 fluxes
     double bu, bT;           // bulk coefficients of the interface flux

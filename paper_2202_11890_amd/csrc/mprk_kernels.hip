@@ -17,8 +17,8 @@
 // routine; the fluxes are exchanged through LDS (aliasing the staged state)
 // and each thread forms the divergence of its cells from its own two face
 // fluxes (registers) and its neighbours' two (LDS).  Three barriers per
-// tile.  One cell per thread keeps the register count low (76 VGPRs in FP64,
-// 48 in FP32), so more waves hide the LDS and HBM latency than with two
+// tile.  One cell per thread keeps the register count low (74 VGPRs in FP64,
+// 50 in FP32), so more waves hide the LDS and HBM latency than with two
 // cells per thread.
 //
 // reduce_*: deterministic (fixed-order) device reductions for the totals,
@@ -117,11 +117,13 @@ __device__ __forceinline__ int pidx(int f, int r, int c) { return (f * S::PZ + r
 // Boundary kinds of a face.
 enum : int { FACE_INTERIOR = 0, FACE_TOP = 1, FACE_BOTTOM = 2 };
 
-// Numerical flux (inviscid minus viscous) through the face between tile cell
-// (c, r) and its +dir neighbour (dir 0: x, 1: z; a constant at the interior
-// call sites, a per-lane value for the edge faces), in the face-normal frame:
-// returns
-// (F_rho, F_normal-momentum, F_tangential-momentum, F_energy), in FT.
+// Twice the numerical flux (inviscid minus viscous) through the face between
+// tile cell (c, r) and its +dir neighbour (dir 0: x, 1: z; a constant at the
+// interior call sites, a per-lane value for the edge faces), in the
+// face-normal frame: returns 2 (F_rho, F_normal-momentum,
+// F_tangential-momentum, F_energy), in FT.  The factor 2 is exact in binary
+// floating point and saves the halvings of the central averages; the
+// divergence takes it back with the half inverse spacings.
 //   kind FACE_TOP:    (c, r) is the top interior row; the other side is its
 //                     mirror (wall or interface).
 //   kind FACE_BOTTOM: (c, r+1) is the bottom interior row; likewise.
@@ -163,22 +165,23 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
     }
 
     // Local Lax-Friedrichs flux, lambda = max(|u_n| + a) over qL, qR and the
-    // Roe average (sqrt(rho)-weighted velocity and total enthalpy).  One
-    // reciprocal square root per side gives 1/rho and sqrt(rho).
-    const FT yL = Fm<FT>::rsqrt(qL[0]), yR = Fm<FT>::rsqrt(qR[0]);
-    const FT rL = yL * yL, rR = yR * yR;
-    const FT sL = qL[0] * yL, sR = qR[0] * yR;
+    // Roe average (sqrt(rho)-weighted velocity and total enthalpy; the
+    // weighted numerators are sqrt(rho) phi = (rho phi) / sqrt(rho)).  One
+    // reciprocal square root per side gives 1/rho, 1/sqrt(rho), sqrt(rho).
+    FT rL, yL, sL, rR, yR, sR;
+    Fm<FT>::inv_sqrt(qL[0], rL, yL, sL);
+    Fm<FT>::inv_sqrt(qR[0], rR, yR, sR);
     const FT unL = qL[1] * rL, utL = qL[2] * rL;
     const FT unR = qR[1] * rR, utR = qR[2] * rR;
     const FT pL = gm1 * fma(-h, fma(qL[1], unL, qL[2] * utL), qL[3]);
     const FT pR = gm1 * fma(-h, fma(qR[1], unR, qR[2] * utR), qR[3]);
+    const FT eL = qL[3] + pL, eR = qR[3] + pR;   // rho H
     const FT aL = Fm<FT>::ws_sqrt(gamma * pL * rL);
     const FT aR = Fm<FT>::ws_sqrt(gamma * pR * rR);
     const FT iw = Fm<FT>::ws_rcp(sL + sR);
-    const FT unr = fma(sL, unL, sR * unR) * iw;
-    const FT utr = fma(sL, utL, sR * utR) * iw;
-    const FT HL = (qL[3] + pL) * rL, HR = (qR[3] + pR) * rR;
-    const FT Hr = fma(sL, HL, sR * HR) * iw;
+    const FT unr = fma(qL[1], yL, qR[1] * yR) * iw;
+    const FT utr = fma(qL[2], yL, qR[2] * yR) * iw;
+    const FT Hr = fma(eL, yL, eR * yR) * iw;
     const FT ar = Fm<FT>::ws_sqrt(gm1 * fma(-h, fma(unr, unr, utr * utr), Hr));
     const FT lam = fmax(fmax(fabs(unL) + aL, fabs(unR) + aR), fabs(unr) + ar);
     if (kind != FACE_INTERIOR) {
@@ -187,46 +190,42 @@ __device__ __forceinline__ void face_flux(const StageArgs& A, const DomainArgs& 
         // the mass, tangential-momentum and energy fluxes at exactly zero,
         // where the general formula leaves rounding residuals.
         F[0] = FT(0);
-        F[1] = (kind == FACE_TOP) ? fma(lam, qL[1], fma(qL[1], unL, pL))
-                                  : fma(-lam, qR[1], fma(qR[1], unR, pR));
+        F[1] = FT(2) * ((kind == FACE_TOP) ? fma(lam, qL[1], fma(qL[1], unL, pL))
+                                           : fma(-lam, qR[1], fma(qR[1], unR, pR)));
         F[2] = FT(0);
         F[3] = FT(0);
         return;
     }
-    const FT hl = h * lam;
-    F[0] = fma(-hl, qR[0] - qL[0], h * (qL[1] + qR[1]));
-    F[1] = fma(-hl, qR[1] - qL[1], h * (fma(qL[1], unL, qR[1] * unR) + (pL + pR)));
-    F[2] = fma(-hl, qR[2] - qL[2], h * fma(qL[2], unL, qR[2] * unR));
-    F[3] = fma(-hl, qR[3] - qL[3], h * fma(qL[3] + pL, unL, (qR[3] + pR) * unR));
+    F[0] = fma(-lam, qR[0] - qL[0], qL[1] + qR[1]);
+    F[1] = fma(-lam, qR[1] - qL[1], fma(qL[1], unL, qR[1] * unR) + (pL + pR));
+    F[2] = fma(-lam, qR[2] - qL[2], fma(qL[2], unL, qR[2] * unR));
+    F[3] = fma(-lam, qR[3] - qL[3], fma(eL, unL, eR * unR));
 
     {
         // Common values: averaged velocity, normal derivative by finite
-        // difference, tangential derivative by averaging cell gradients.
+        // difference, tangential derivative by averaging cell gradients; the
+        // spacings and mu, kappa are folded into the coefficients vk.
         const int pb = pidx<S>(0, r, c);
         const int pn = dir ? PX : 1;
         const int pt = dir ? 1 : PX;
         const int fn = dir ? 1 : 0;          // normal velocity in the primitive tile
         const int ft = dir ? 0 : 1;
+        // Coefficient of the normal (n) or tangential (t) direction: both are
+        // read as uniform arguments and selected per lane (edge faces).
+        auto vkn = [&](int row) { const FT x = arg_vk<FT>(D, row, 0), z = arg_vk<FT>(D, row, 2); return dir ? z : x; };
+        auto vkt = [&](int row) { const FT x = arg_vk<FT>(D, row, 0), z = arg_vk<FT>(D, row, 2); return dir ? x : z; };
         constexpr int pp = PZ * PX;
         const FT* Un = L.p + fn * pp + pb;
         const FT* Ut = L.p + ft * pp + pb;
         const FT* Tt = L.p + 2 * pp + pb;
-        const FT inv_x = arg_ft<FT>(A.inv_dx, A.inv_dx_f), inv_z = arg_ft<FT>(D.inv_dz, D.inv_dz_f);
-        const FT inv_n = dir ? inv_z : inv_x;
-        const FT inv_t4 = q4 * (dir ? inv_x : inv_z);
         const FT unA = Un[0], unB = Un[pn], utA = Ut[0], utB = Ut[pn];
-        const FT dn_un = (unB - unA) * inv_n;
-        const FT dn_ut = (utB - utA) * inv_n;
-        const FT dn_T = (Tt[pn] - Tt[0]) * inv_n;
-        const FT dt_un = ((Un[pt] - Un[-pt]) + (Un[pn + pt] - Un[pn - pt])) * inv_t4;
-        const FT dt_ut = ((Ut[pt] - Ut[-pt]) + (Ut[pn + pt] - Ut[pn - pt])) * inv_t4;
-        const FT mu = arg_ft<FT>(D.mu, D.mu_f);
-        const FT snn = mu * fma(FT(4.0 / 3.0), dn_un, FT(-2.0 / 3.0) * dt_ut);
-        const FT snt = mu * (dn_ut + dt_un);
-        F[1] = F[1] - snn;
-        F[2] = F[2] - snt;
-        const FT kappa = arg_ft<FT>(D.kappa, D.kappa_f);
-        F[3] = F[3] - fma(h * (unA + unB), snn, fma(h * (utA + utB), snt, kappa * dn_T));
+        const FT t_un = (Un[pt] - Un[-pt]) + (Un[pn + pt] - Un[pn - pt]);
+        const FT t_ut = (Ut[pt] - Ut[-pt]) + (Ut[pn + pt] - Ut[pn - pt]);
+        const FT snn = fma(vkn(VK_NN), unB - unA, vkt(VK_TT) * t_ut);
+        const FT snt = fma(vkn(VK_N), utB - utA, vkt(VK_TN) * t_un);
+        F[1] = fma(FT(-2), snn, F[1]);
+        F[2] = fma(FT(-2), snt, F[2]);
+        F[3] = F[3] - fma(unA + unB, snn, fma(utA + utB, snt, vkn(VK_Q) * (Tt[pn] - Tt[0])));
     }
 }
 
@@ -482,8 +481,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, int tile, char* s
         for (int v = 0; v < NV; ++v) {
             const FT* fx = ex_x + v * TZ * (TX + 1) + r * (TX + 1) + c;
             const FT* fz = ex_z + v * (TZ + 1) * TX + r * TX + c;
-            R[v] = -((double)F[h][v] - (double)fx[0]) * A.inv_dx -
-                   ((double)F[CZ + h][zmap[v]] - (double)fz[0]) * D.inv_dz;
+            R[v] = -((double)F[h][v] - (double)fx[0]) * A.hinv_dx -
+                   ((double)F[CZ + h][zmap[v]] - (double)fz[0]) * D.hinv_dz;
         }
         // Interface viscous flux (FP64, same bits on both sides): it leaves the
         // lower domain through its top face and enters the upper domain
