@@ -85,10 +85,10 @@ enum mprk_exec {
  * Results do not depend on the shape: every face is evaluated by the same
  * operations whichever tile holds it. */
 enum mprk_tile {
-    MPRK_TILE_32X16 = 0,      /* default with FP64 fluxes (and in 3D) */
+    MPRK_TILE_32X16 = 0,      /* default (2D with either flux precision, and 3D) */
     MPRK_TILE_16X32 = 1,
     MPRK_TILE_64X8 = 2,
-    MPRK_TILE_32X8 = 3,       /* default with FP32 fluxes in 2D */
+    MPRK_TILE_32X8 = 3,
     MPRK_TILE_SHAPES = 4
 };
 
@@ -255,10 +255,10 @@ int mprk_set_exec(mprk_ctx* ctx, int mode);
  * one tile's work.  0 aborts at the first wait that is not already met. */
 int mprk_set_wait_limit(mprk_ctx* ctx, double seconds);
 
-/* Tile shape of later launches (an mprk_tile value; default MPRK_TILE_32X16
- * with FP64 fluxes, MPRK_TILE_32X8 with FP32 fluxes).  Results are
- * bit-identical for every shape.  3D contexts have one tile shape per flux
- * precision, selected by MPRK_TILE_32X16 (other values: MPRK_EUNSUPPORTED). */
+/* Tile shape of later launches (an mprk_tile value; default MPRK_TILE_32X16).
+ * Results are bit-identical for every shape.  3D contexts have one tile shape
+ * per flux precision, selected by MPRK_TILE_32X16 (other values:
+ * MPRK_EUNSUPPORTED). */
 int mprk_set_tile(mprk_ctx* ctx, int shape);
 
 /* Kernel timing aid.  While enabled, every stage launch is bracketed by a

@@ -48,12 +48,11 @@ int shu_osher(int base, double* alpha)
 
 int tiles_of(int n, int t) { return (n + t - 1) / t; }
 
-// Default 2D tile shape per flux precision (measured on the 1024x512
-// workload: 32x16 fastest with FP64 fluxes, 32x8 with FP32 fluxes, which need
-// half the LDS per tile).  3D contexts ignore the 2D shape.
-int default_shape(const mprk_config& c)
+// Default 2D tile shape (measured on the 1024x512 workload: 32x16 is the
+// fastest with FP64 and with FP32 fluxes).  3D contexts ignore the 2D shape.
+int default_shape(const mprk_config&)
 {
-    return (c.dim == 2 && c.flux_bits == 32) ? TILE_32x8 : TILE_32x16;
+    return TILE_32x16;
 }
 
 int nv_of(const mprk_config& c) { return c.dim == 3 ? NV3 : NV; }
