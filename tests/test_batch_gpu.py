@@ -104,14 +104,18 @@ def test_batch_modes_bitwise(mode):
     assert all(same(a, b) for a, b in zip(ref, got))
 
 
+@pytest.mark.parametrize("flux_bits", [64, 32])
 @pytest.mark.parametrize("tile", [mprk.TILE_16X32, mprk.TILE_64X8, mprk.TILE_32X8])
-def test_tile_shapes_bitwise(tile):
+def test_tile_shapes_bitwise(tile, flux_bits):
+    """Every tile shape gives the default shape's bits, with either flux
+    precision (a face on a tile edge is computed by the same operations
+    whichever tile and call site computes it)."""
     sts = states(MEMBERS)
-    ref = run_batch(sts, 5)
-    got = run_batch(sts, 5, tile=tile)
+    ref = run_batch(sts, 5, flux_bits)
+    got = run_batch(sts, 5, flux_bits, tile=tile)
     assert all(same(a, b) for a, b in zip(ref, got))
     w, ql, qu, dt = sts[1]
-    assert same(run_single(w, ql, qu, dt, 5, tile=tile), run_single(w, ql, qu, dt, 5))
+    assert same(run_single(w, ql, qu, dt, 5, flux_bits, tile=tile), run_single(w, ql, qu, dt, 5, flux_bits))
 
 
 @pytest.mark.parametrize("tile", [mprk.TILE_16X32, mprk.TILE_32X8])
