@@ -2,7 +2,12 @@
 // dimensions (Appendix B, eq. ns-fv-cartesian-3d: x and y periodic, the two
 // domains stacked in z and coupled through the rigid lid).
 //
-// Same structure as the 2D kernel: a workgroup owns a TX x TY x TZ tile of one
+// Two kernels.  march_kernel3 (FP32 face fluxes, the 3D workload's precision)
+// walks 32 x 8 columns of one domain upward through a z-segment, plane by
+// plane, with a rolling window of staged planes in LDS.  stage_kernel3 (FP64
+// face fluxes) is the brick form described next.
+//
+// Brick form, the 2D kernel's structure: a workgroup owns a TX x TY x TZ tile of one
 // domain; each thread owns one cell (or a vertical run of cells).  The conserved state
 // (5 components, 2-cell halo) and the primitives u, v, w, T (1-cell halo) are
 // staged in LDS in the flux type; every face of the tile is evaluated once
@@ -46,14 +51,10 @@ struct Shape3 {
     static constexpr int lds_bytes() { return (LDS_Q + LDS_P) * (int)sizeof(FT) + 3 * X * Y * 8; }
 };
 
-#ifndef MPRK3_CZ32
-#define MPRK3_CZ32 1
-#endif
-using T32 = Shape3<16, 8, 4, MPRK3_CZ32>;   // FP32 fluxes: 58.8 KB LDS
 using T64 = Shape3<16, 4, 4, 1>;            // FP64 fluxes: 73.5 KB LDS, 256 threads
 
+// Brick tile per flux type (FP32 fluxes run the marching kernel instead).
 template <class FT> struct TileOf;
-template <> struct TileOf<float> { using S = T32; };
 template <> struct TileOf<double> { using S = T64; };
 
 template <class FT>
