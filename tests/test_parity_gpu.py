@@ -95,6 +95,11 @@ CASES_RHS = [
     ("gravity", inputs.small().with_(nx=36, nz_lower=18, nz_upper=22, gravity=-0.05,
                                      mu_lower=3e-3, mu_upper=4e-4)),
     ("tiny", inputs.small().with_(nx=5, nz_lower=3, nz_upper=4, n_buffer=1)),
+    # viscous fluxes of the order of the inviscid ones (fine anisotropic grid,
+    # large and unequal viscosities): the viscous coefficients per direction
+    # and domain at full weight
+    ("viscous", inputs.small().with_(nx=30, nz_lower=16, nz_upper=14, lx=1.0, lz_lower=0.8, lz_upper=0.5,
+                                     mu_lower=0.05, mu_upper=0.02)),
 ]
 
 
@@ -178,6 +183,8 @@ CASES_RUN = [
     ("gravity-rk3", inputs.small().with_(nx=36, nz_lower=18, nz_upper=22, gravity=-0.05,
                                          base=3, m=2, n_buffer=6), 30),
     ("tiny-nb1", inputs.small().with_(nx=5, nz_lower=3, nz_upper=4, n_buffer=1, m=8), 20),
+    ("viscous-rk3", inputs.small().with_(nx=30, nz_lower=16, nz_upper=14, lx=1.0, lz_lower=0.8, lz_upper=0.5,
+                                         mu_lower=0.05, mu_upper=0.02, base=3, m=2, n_buffer=5), 30),
 ]
 
 
