@@ -42,6 +42,8 @@ CASES_RHS = [
                                         t_lower=1.0, t_upper=16.0)),
     ("gravity", inputs.small().with_(nx=36, nz_lower=18, nz_upper=22, gravity=-0.05,
                                      mu_lower=3e-3, mu_upper=4e-4)),
+    ("viscous", inputs.small().with_(nx=30, nz_lower=16, nz_upper=14, lx=1.0, lz_lower=0.8, lz_upper=0.5,
+                                     mu_lower=0.05, mu_upper=0.02)),
 ]
 
 
@@ -91,6 +93,8 @@ CASES_RUN = [
     ("rk3-m4", inputs.small().with_(base=3, m=4, n_buffer=5), 30),
     ("fast-upper", inputs.small().with_(nx=45, nz_lower=33, nz_upper=18, fast_is_lower=False,
                                         t_lower=1.0, t_upper=16.0, n_buffer=3), 30),
+    ("viscous-rk3", inputs.small().with_(nx=30, nz_lower=16, nz_upper=14, lx=1.0, lz_lower=0.8, lz_upper=0.5,
+                                         mu_lower=0.05, mu_upper=0.02, base=3, m=2, n_buffer=5), 30),
 ]
 
 
