@@ -41,7 +41,7 @@ def parse():
                     help="persistent: one cooperative launch per check segment; launch: one per stage")
     ap.add_argument("--tile", choices=["32x16", "16x32", "64x8", "32x8"], default=None,
                     help="2D tile shape of the headline, FP32-flux and single-rate runs (default: the "
-                         "library's, 32x16 with FP64 fluxes and 32x8 with FP32 fluxes)")
+                         "library's, 32x16)")
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-sr", action="store_true", help="skip the single-rate comparison")
@@ -345,13 +345,16 @@ def main():
         # values and sums are FP64 either way); launch mode only.
         launch32_s = gpu32_ms * 1e-3 / (K * launches_per_step)
         ach32 = bytes_step / launches_per_step / launch32_s / 1e9
+        # counter bytes of the FP32 instantiation (default tile) from its own summary
+        t32 = traffic_from_profiles("fp32flux_" + args.workload) if args.tile in (None, "32x16") else None
         out["fp32_flux"] = {
             "value": cs_step * K / t_32, "ms_per_step": 1e3 * t_32 / K, "status": fst["status"],
-            "speedup_vs_f64": t_mprk / t_32, "tile": args.tile or "32x8",
+            "speedup_vs_f64": t_mprk / t_32, "tile": args.tile or "32x16",
             "max_rel_diff_vs_f64": {"lower": dif[0], "upper": dif[1]},
             "roofline": None if args.exec != "launch" else {
                 "bound": "hbm", "kernel": "stage_kernel (FP32 fluxes)", "achieved": round(ach32, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach32 / HBM_PEAK_GBS, 4),
+                "traffic": t32, "traffic_gbs": None if t32 is None else round(t32 / launch32_s / 1e9, 1),
                 "avg_launch_us": round(launch32_s * 1e6, 3)},
         }
         print("# fp32 flux: %.1f us/step, speedup %.3f" % (1e6 * t_32 / K, t_mprk / t_32),
