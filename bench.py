@@ -641,6 +641,8 @@ def ensemble_leg(args, torch, dev):
     if args.ensemble_mode is not None:
         mode = {"graph": mprk.EXEC_GRAPH, "launch": mprk.EXEC_LAUNCH,
                 "persistent": mprk.EXEC_PERSISTENT}[args.ensemble_mode]
+        # a fixed tile (within 0.1% of the tuner's pick on this ensemble), so
+        # that one-mode runs profiled separately share their tile shape
         batch.set_tile(mprk.TILE_32X8)
         batch.set_exec(mode)
         batch.set_adaptive(cr, dn)
