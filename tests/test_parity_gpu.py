@@ -185,6 +185,7 @@ CASES_RUN = [
     ("tiny-nb1", inputs.small().with_(nx=5, nz_lower=3, nz_upper=4, n_buffer=1, m=8), 20),
     ("viscous-rk3", inputs.small().with_(nx=30, nz_lower=16, nz_upper=14, lx=1.0, lz_lower=0.8, lz_upper=0.5,
                                          mu_lower=0.05, mu_upper=0.02, base=3, m=2, n_buffer=5), 30),
+    ("rk3-m8", inputs.small().with_(nx=41, nz_lower=23, nz_upper=19, base=3, m=8, n_buffer=5), 12),
 ]
 
 
